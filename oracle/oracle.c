@@ -1,0 +1,716 @@
+/*
+ * FP64 CPU oracle for the fused lattice Boltzmann stream-and-collide step.
+ *
+ * TEST INFRASTRUCTURE ONLY: the plain reference the HIP path is checked
+ * against.  Only tests, the smoke check and the benchmark's CPU-baseline leg
+ * load it.  It shares no code with the HIP library.
+ *
+ * Every step is written the plain way: gather a node's populations, collide
+ * them (or swap them on a wall node), push each post-collision value to
+ * x + e_i in a second array, swap arrays.  All arithmetic is double precision.
+ * Citations name the section / equation of Januszewski & Kostur, "Sailfish: a
+ * flexible multi-GPU implementation of the lattice Boltzmann method" (CPC 2014).
+ *
+ * Readings of points the paper leaves open (each also listed in the design notes):
+ *  - LBGK sign: the relaxation is f + (1/tau)(feq - f), as in the GPU kernel
+ *    algorithm of the software section; the sign printed in the LBGK equation is
+ *    the unstable one.
+ *  - The body force is an acceleration g; the force density is F = rho g.
+ *  - MRT basis: the orthogonal polynomial moments of d'Humieres et al. (2002)
+ *    (cited by the paper for M), m_eq = M f_eq, the Guo source relaxed as
+ *    (I - S/2) M F~.
+ *  - ELBM equilibrium: the product form with the factor (2 - sqrt(1+3u^2)) is
+ *    exact on D2Q9; on D3Q19 the exact discrete H minimiser w_i exp(b.e_i)/Z is
+ *    used, seeded with the product form's b and refined by two Newton steps.
+ *  - ELBM relaxation f + alpha beta (feq - f), beta = 1/(2 tau), so alpha = 2 is LBGK.
+ *  - Shan-Chen force F_A = -G psi_A sum_i w_i psi_B(x+e_i) e_i (G > 0 repulsive),
+ *    EDM forcing around the common velocity.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define QMAX 19
+#define MLP_H 32
+#define MLP_IN 6
+#define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1)
+
+typedef struct {
+    int q, d;
+    int e[QMAX][3];
+    double w[QMAX];
+    int opp[QMAX];
+} lattice_t;
+
+/* Velocity sets in the ordering documented in oracle.h. */
+static const int VEL_D2Q9[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}};
+static const int VEL_D3Q19[19][3] = {
+    {0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+/* Weights by link length (rest, 1, sqrt 2): the paper's weight table. */
+static void make_lattice(int lattice, lattice_t *L) {
+    const double wd2q9[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
+    const double wd3q19[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    const double *wl = lattice == ORC_D2Q9 ? wd2q9 : wd3q19;
+    L->q = lattice == ORC_D2Q9 ? 9 : 19;
+    L->d = lattice == ORC_D2Q9 ? 2 : 3;
+    for (int i = 0; i < L->q; i++) {
+        const int *v = lattice == ORC_D2Q9 ? VEL_D2Q9[i] : VEL_D3Q19[i];
+        int len2 = 0;
+        for (int a = 0; a < 3; a++) {
+            L->e[i][a] = v[a];
+            len2 += v[a] * v[a];
+        }
+        L->w[i] = wl[len2];
+    }
+    /* opposite direction found by search for -e_i */
+    for (int i = 0; i < L->q; i++)
+        for (int j = 0; j < L->q; j++)
+            if (L->e[j][0] == -L->e[i][0] && L->e[j][1] == -L->e[i][1] && L->e[j][2] == -L->e[i][2])
+                L->opp[i] = j;
+}
+
+int orc_q(int lattice) { return lattice == ORC_D2Q9 ? 9 : 19; }
+
+void orc_tables(int lattice, int *e, double *w, int *opp) {
+    lattice_t L;
+    make_lattice(lattice, &L);
+    for (int i = 0; i < L.q; i++) {
+        for (int a = 0; a < 3; a++) e[3 * i + a] = L.e[i][a];
+        w[i] = L.w[i];
+        opp[i] = L.opp[i];
+    }
+}
+
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---- equilibria ----------------------------------------------------------- */
+
+/* Second-order polynomial equilibrium (equilibrium equation of section 2). */
+static void feq_poly(const lattice_t *L, double rho, const double *u, double *feq) {
+    double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < L->q; i++) {
+        double eu = L->e[i][0] * u[0] + L->e[i][1] * u[1] + L->e[i][2] * u[2];
+        feq[i] = rho * L->w[i] * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+    }
+}
+
+void orc_feq(int lattice, double rho, const double *u, double *feq) {
+    lattice_t L;
+    make_lattice(lattice, &L);
+    feq_poly(&L, rho, u, feq);
+}
+
+/* Solve the d x d system A x = r (d = 2 or 3) by Cramer's rule. */
+static void solve_small(int d, double A[3][3], const double *r, double *x) {
+    if (d == 2) {
+        double det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        x[0] = (r[0] * A[1][1] - A[0][1] * r[1]) / det;
+        x[1] = (A[0][0] * r[1] - r[0] * A[1][0]) / det;
+        x[2] = 0.0;
+        return;
+    }
+    double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1])
+               - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0])
+               + A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    for (int c = 0; c < 3; c++) {
+        double B[3][3];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) B[a][b] = (b == c) ? r[a] : A[a][b];
+        x[c] = (B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1])
+              - B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0])
+              + B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0])) / det;
+    }
+}
+
+/* Discrete entropic equilibrium: the minimiser of H = sum f ln(f/w) at fixed
+ * rho and rho u (entropic LBM subsection).  Its form is rho w_i exp(b.e_i)/Z.
+ * The first guess b_a = ln((2u_a + sqrt(1+3u_a^2))/(1-u_a)) is the product form's
+ * exponent base; two Newton steps on the momentum constraint follow (Jacobian =
+ * covariance of e under the normalised weights). */
+static void feq_entropic(const lattice_t *L, double rho, const double *u, double *feq) {
+    double b[3] = {0.0, 0.0, 0.0};
+    double p[QMAX];
+    for (int a = 0; a < L->d; a++) {
+        double s = sqrt(1.0 + 3.0 * u[a] * u[a]);
+        b[a] = log((2.0 * u[a] + s) / (1.0 - u[a]));
+    }
+    for (int it = 0; it < 2; it++) {
+        double Z = 0.0, m[3] = {0, 0, 0}, C[3][3] = {{0}};
+        for (int i = 0; i < L->q; i++) {
+            p[i] = L->w[i] * exp(b[0] * L->e[i][0] + b[1] * L->e[i][1] + b[2] * L->e[i][2]);
+            Z += p[i];
+        }
+        for (int i = 0; i < L->q; i++) {
+            p[i] /= Z;
+            for (int a = 0; a < 3; a++) {
+                m[a] += p[i] * L->e[i][a];
+                for (int c = 0; c < 3; c++) C[a][c] += p[i] * L->e[i][a] * L->e[i][c];
+            }
+        }
+        double r[3], db[3];
+        for (int a = 0; a < 3; a++) {
+            r[a] = m[a] - u[a];
+            for (int c = 0; c < 3; c++) C[a][c] -= m[a] * m[c];
+        }
+        solve_small(L->d, C, r, db);
+        for (int a = 0; a < L->d; a++) b[a] -= db[a];
+    }
+    double Z = 0.0;
+    for (int i = 0; i < L->q; i++) {
+        p[i] = L->w[i] * exp(b[0] * L->e[i][0] + b[1] * L->e[i][1] + b[2] * L->e[i][2]);
+        Z += p[i];
+    }
+    for (int i = 0; i < L->q; i++) feq[i] = rho * p[i] / Z;
+}
+
+void orc_feq_entropic(int lattice, double rho, const double *u, double *feq) {
+    lattice_t L;
+    make_lattice(lattice, &L);
+    feq_entropic(&L, rho, u, feq);
+}
+
+/* ---- MRT moment basis ---------------------------------------------------- */
+
+/* Rows of the orthogonal moment matrix (d'Humieres et al. 2002, the reference
+ * the MRT subsection gives for M), as polynomials of e with q = |e|^2. */
+static double mrt_row(int lattice, int k, const int *e) {
+    double ex = e[0], ey = e[1], ez = e[2];
+    double q = ex * ex + ey * ey + ez * ez;
+    if (lattice == ORC_D2Q9) {
+        switch (k) {
+        case 0: return 1.0;
+        case 1: return 3.0 * q - 4.0;
+        case 2: return (9.0 * q * q - 21.0 * q + 8.0) / 2.0;
+        case 3: return ex;
+        case 4: return (3.0 * q - 5.0) * ex;
+        case 5: return ey;
+        case 6: return (3.0 * q - 5.0) * ey;
+        case 7: return ex * ex - ey * ey;
+        default: return ex * ey;
+        }
+    }
+    switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * q - 30.0;
+    case 2: return (21.0 * q * q - 53.0 * q + 24.0) / 2.0;
+    case 3: return ex;
+    case 4: return (5.0 * q - 9.0) * ex;
+    case 5: return ey;
+    case 6: return (5.0 * q - 9.0) * ey;
+    case 7: return ez;
+    case 8: return (5.0 * q - 9.0) * ez;
+    case 9: return 3.0 * ex * ex - q;
+    case 10: return (3.0 * q - 5.0) * (3.0 * ex * ex - q);
+    case 11: return ey * ey - ez * ez;
+    case 12: return (3.0 * q - 5.0) * (ey * ey - ez * ez);
+    case 13: return ex * ey;
+    case 14: return ey * ez;
+    case 15: return ex * ez;
+    case 16: return (ey * ey - ez * ez) * ex;
+    case 17: return (ez * ez - ex * ex) * ey;
+    default: return (ex * ex - ey * ey) * ez;
+    }
+}
+
+static void mrt_build(int lattice, const lattice_t *L, double M[QMAX][QMAX], double norm2[QMAX]) {
+    for (int k = 0; k < L->q; k++) {
+        norm2[k] = 0.0;
+        for (int i = 0; i < L->q; i++) {
+            M[k][i] = mrt_row(lattice, k, L->e[i]);
+            norm2[k] += M[k][i] * M[k][i];
+        }
+    }
+}
+
+void orc_mrt_matrix(int lattice, double *Mout) {
+    lattice_t L;
+    double M[QMAX][QMAX], n2[QMAX];
+    make_lattice(lattice, &L);
+    mrt_build(lattice, &L, M, n2);
+    for (int k = 0; k < L.q; k++)
+        for (int i = 0; i < L.q; i++) Mout[k * L.q + i] = M[k][i];
+}
+
+/* ---- ELBM ------------------------------------------------------------------- */
+
+static double H_of(const lattice_t *L, const double *f) {
+    double h = 0.0;
+    for (int i = 0; i < L->q; i++) h += f[i] * log(f[i] / L->w[i]);
+    return h;
+}
+
+double orc_H(int lattice, const double *f) {
+    lattice_t L;
+    make_lattice(lattice, &L);
+    return H_of(&L, f);
+}
+
+/* g(a) = H(f + a D) - H(f) and g'(a), D = feq - f, in a form free of the
+ * cancellation between the two H values (uses sum_i D_i ln(feq_i/w_i) = 0,
+ * which holds because feq is the constrained minimiser and D carries no mass
+ * or momentum). */
+static void g_dg(int q, const double *f, const double *D, double a, double *g, double *dg) {
+    double s = 0.0, ds = 0.0;
+    for (int i = 0; i < q; i++) {
+        double la = log1p(a * D[i] / f[i]);
+        double l1 = log1p(D[i] / f[i]);
+        s += (f[i] + a * D[i]) * la - a * D[i] * l1;
+        ds += D[i] * (la - l1);
+    }
+    *g = s;
+    *dg = ds;
+}
+
+void orc_alpha_features(int lattice, const double *f, const double *feq, double rho, double vsq,
+                        double *feat) {
+    int q = orc_q(lattice);
+    double a2 = 0, a3 = 0, a4 = 0, mneg = -1e300, mpos = -1e300;
+    for (int i = 0; i < q; i++) {
+        double d = (feq[i] - f[i]) / f[i];
+        a2 += f[i] * d * d;
+        a3 += f[i] * d * d * d;
+        a4 += f[i] * d * d * d * d;
+        if (-d > mneg) mneg = -d;
+        if (d > mpos) mpos = d;
+    }
+    feat[0] = log10(a2 / rho);
+    feat[1] = a3 / a2;
+    feat[2] = a4 / a2;
+    feat[3] = mneg;
+    feat[4] = mpos;
+    feat[5] = 3.0 * vsq;
+}
+
+/* MLP 6 -> 32 -> 32 -> 1, tanh hidden layers, output 2 + linear.
+ * Parameter layout: W1[32][6], b1[32], W2[32][32], b2[32], w3[32], b3. */
+static double mlp_eval(const double *p, const double *x, double *h1, double *h2) {
+    const double *W1 = p, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    const double *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
+    for (int j = 0; j < MLP_H; j++) {
+        double s = b1[j];
+        for (int k = 0; k < MLP_IN; k++) s += W1[j * MLP_IN + k] * x[k];
+        h1[j] = tanh(s);
+    }
+    for (int j = 0; j < MLP_H; j++) {
+        double s = b2[j];
+        for (int k = 0; k < MLP_H; k++) s += W2[j * MLP_H + k] * h1[k];
+        h2[j] = tanh(s);
+    }
+    double y = 2.0 + b3[0];
+    for (int k = 0; k < MLP_H; k++) y += w3[k] * h2[k];
+    return y;
+}
+
+void orc_mlp_forward(const double *p, const double *x, int64_t n, double *y) {
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < n; r++) {
+        double h1[MLP_H], h2[MLP_H];
+        y[r] = mlp_eval(p, x + MLP_IN * r, h1, h2);
+    }
+}
+
+/* Mean squared error (1/n) sum (y - t)^2 and its gradient by back-propagation. */
+double orc_mlp_loss_grad(const double *p, const double *x, const double *t, int64_t n, double *grad) {
+    const double *W2 = p + MLP_H * MLP_IN + MLP_H;
+    const double *w3 = W2 + MLP_H * MLP_H + MLP_H;
+    double loss = 0.0;
+    memset(grad, 0, sizeof(double) * MLP_NPARAM);
+    for (int64_t r = 0; r < n; r++) {
+        double h1[MLP_H], h2[MLP_H], d2[MLP_H], d1[MLP_H];
+        const double *xr = x + MLP_IN * r;
+        double y = mlp_eval(p, xr, h1, h2);
+        double err = y - t[r];
+        loss += err * err;
+        double dy = 2.0 * err / (double)n;
+        double *gW1 = grad, *gb1 = gW1 + MLP_H * MLP_IN, *gW2 = gb1 + MLP_H, *gb2 = gW2 + MLP_H * MLP_H;
+        double *gw3 = gb2 + MLP_H, *gb3 = gw3 + MLP_H;
+        gb3[0] += dy;
+        for (int j = 0; j < MLP_H; j++) {
+            gw3[j] += dy * h2[j];
+            d2[j] = dy * w3[j] * (1.0 - h2[j] * h2[j]);
+        }
+        for (int j = 0; j < MLP_H; j++) {
+            gb2[j] += d2[j];
+            for (int k = 0; k < MLP_H; k++) gW2[j * MLP_H + k] += d2[j] * h1[k];
+        }
+        for (int k = 0; k < MLP_H; k++) {
+            double s = 0.0;
+            for (int j = 0; j < MLP_H; j++) s += W2[j * MLP_H + k] * d2[j];
+            d1[k] = s * (1.0 - h1[k] * h1[k]);
+        }
+        for (int j = 0; j < MLP_H; j++) {
+            gb1[j] += d1[j];
+            for (int k = 0; k < MLP_IN; k++) gW1[j * MLP_IN + k] += d1[j] * xr[k];
+        }
+    }
+    return loss / (double)n;
+}
+
+/* Nontrivial root alpha of H(f + alpha (feq - f)) = H(f) (alpha condition of the
+ * entropic LBM subsection).  Close to equilibrium (max |D_i/f_i| < 1e-6) the
+ * root is taken as 2, the value the paper gives for that limit.  Otherwise a
+ * safeguarded Newton iteration: the bracket starts at [1, alpha_max) where
+ * g(1) = H(feq) - H(f) <= 0 and alpha_max keeps every population positive;
+ * stop when the Newton step |d alpha| <= tol, otherwise a Newton iterate
+ * outside the bracket is replaced by the bracket's midpoint.  No convergence within maxit: alpha = min(2, 0.99 alpha_max). */
+double orc_alpha(int lattice, const double *f, const double *feq, int init, const double *mlp,
+                 double vsq, double tol, int maxit, int *iters, int *converged) {
+    int q = orc_q(lattice);
+    double D[QMAX], dmax = 0.0, amax = INFINITY;
+    for (int i = 0; i < q; i++) {
+        D[i] = feq[i] - f[i];
+        double r = fabs(D[i] / f[i]);
+        if (r > dmax) dmax = r;
+        if (D[i] < 0.0 && -f[i] / D[i] < amax) amax = -f[i] / D[i];
+    }
+    *converged = 1;
+    *iters = 0;
+    if (dmax < 1e-6) return 2.0;
+
+    double a0 = 2.0;
+    if (init == 1) {
+        double a2 = 0, a3 = 0, a4 = 0;
+        for (int i = 0; i < q; i++) {
+            double d = D[i] / f[i];
+            a2 += f[i] * d * d;
+            a3 += f[i] * d * d * d;
+            a4 += f[i] * d * d * d * d;
+        }
+        a0 = 2.0 + (a3 - 2.0 * a4) / (3.0 * a2);
+    } else if (init == 2 && mlp) {
+        double feat[MLP_IN], h1[MLP_H], h2[MLP_H], rho = 0.0;
+        for (int i = 0; i < q; i++) rho += f[i];
+        orc_alpha_features(lattice, f, feq, rho, vsq, feat);
+        a0 = mlp_eval(mlp, feat, h1, h2);
+    }
+    double lo = 1.0, hi = amax, a = a0;
+    if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
+    for (int k = 1; k <= maxit; k++) {
+        double g, dg;
+        g_dg(q, f, D, a, &g, &dg);
+        if (g == 0.0) {
+            *iters = k;
+            return a;
+        }
+        if (g < 0.0) lo = a; else hi = a;
+        double an = a - g / dg;
+        if (fabs(an - a) <= tol) {
+            *iters = k;
+            return an;
+        }
+        if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
+        a = an;
+    }
+    *converged = 0;
+    *iters = maxit;
+    return amax * 0.99 < 2.0 ? amax * 0.99 : 2.0;
+}
+
+/* ---- collision ---------------------------------------------------------------- */
+
+/* Guo source term without its (1 - 1/(2 tau)) prefactor (body forces section):
+ * w_i [3 (e_i - v) + 9 (e_i . v) e_i] . F. */
+static void guo_source(const lattice_t *L, const double *v, const double *F, double *Fi) {
+    for (int i = 0; i < L->q; i++) {
+        double ev = L->e[i][0] * v[0] + L->e[i][1] * v[1] + L->e[i][2] * v[2];
+        double s = 0.0;
+        for (int a = 0; a < 3; a++) s += (3.0 * (L->e[i][a] - v[a]) + 9.0 * ev * L->e[i][a]) * F[a];
+        Fi[i] = L->w[i] * s;
+    }
+}
+
+static void moments(const lattice_t *L, const double *f, double *rho, double *j) {
+    double r = 0.0;
+    j[0] = j[1] = j[2] = 0.0;
+    for (int i = 0; i < L->q; i++) {
+        r += f[i];
+        for (int a = 0; a < 3; a++) j[a] += L->e[i][a] * f[i];
+    }
+    *rho = r;
+}
+
+typedef struct {
+    int iters, converged;
+} node_info;
+
+/* One fluid node's collision for BGK, MRT or ELBM. */
+static void collide_single(const orc_params *P, const lattice_t *L, const double *f, double *out,
+                           node_info *info) {
+    int q = L->q;
+    double rho, j[3], F[3], v[3], feq[QMAX];
+    moments(L, f, &rho, j);
+    if (P->model == ORC_ELBM) {
+        for (int a = 0; a < 3; a++) v[a] = j[a] / rho;
+        feq_entropic(L, rho, v, feq);
+        double vsq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        int it, conv;
+        double alpha = orc_alpha(P->lattice, f, feq, P->alpha_init, P->mlp, vsq, P->alpha_tol,
+                                 P->alpha_maxit, &it, &conv);
+        if (info) {
+            info->iters = it;
+            info->converged = conv;
+        }
+        double beta = 1.0 / (2.0 * P->tau);
+        for (int i = 0; i < q; i++) out[i] = f[i] + alpha * beta * (feq[i] - f[i]);
+        return;
+    }
+    for (int a = 0; a < 3; a++) {
+        F[a] = rho * P->g[a];
+        v[a] = (j[a] + 0.5 * F[a]) / rho;
+    }
+    feq_poly(L, rho, v, feq);
+    double Fi[QMAX];
+    guo_source(L, v, F, Fi);
+    if (P->model == ORC_BGK) {
+        double omega = 1.0 / P->tau, pre = 1.0 - 1.0 / (2.0 * P->tau);
+        for (int i = 0; i < q; i++) out[i] = f[i] + omega * (feq[i] - f[i]) + pre * Fi[i];
+        return;
+    }
+    /* MRT: m = M f, m* = m - S (m - m_eq) + (I - S/2) M F~, f* = M^-1 m*,
+     * with M^-1 = M^T diag(1/|row|^2) for the orthogonal basis. */
+    double M[QMAX][QMAX], n2[QMAX], m[QMAX], meq[QMAX], mF[QMAX], ms[QMAX];
+    mrt_build(P->lattice, L, M, n2);
+    for (int k = 0; k < q; k++) {
+        m[k] = meq[k] = mF[k] = 0.0;
+        for (int i = 0; i < q; i++) {
+            m[k] += M[k][i] * f[i];
+            meq[k] += M[k][i] * feq[i];
+            mF[k] += M[k][i] * Fi[i];
+        }
+        ms[k] = m[k] - P->s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * P->s[k]) * mF[k];
+    }
+    for (int i = 0; i < q; i++) {
+        double s = 0.0;
+        for (int k = 0; k < q; k++) s += M[k][i] * ms[k] / n2[k];
+        out[i] = s;
+    }
+}
+
+void orc_collide_node(const orc_params *P, const double *f, double *out) {
+    lattice_t L;
+    make_lattice(P->lattice, &L);
+    collide_single(P, &L, f, out, NULL);
+}
+
+/* ---- full-lattice operations ------------------------------------------------------ */
+
+static int check_params(const orc_params *P) {
+    if (P->lattice != ORC_D2Q9 && P->lattice != ORC_D3Q19) return -1;
+    if (P->model < ORC_BGK || P->model > ORC_SHANCHEN) return -1;
+    if (P->nx <= 0 || P->ny <= 0 || P->nz <= 0) return -1;
+    if (P->lattice == ORC_D2Q9 && P->nz != 1) return -1;
+    if (!(P->tau > 0.5)) return -1;
+    if (P->model == ORC_ELBM && (P->g[0] != 0.0 || P->g[1] != 0.0 || P->g[2] != 0.0)) return -1;
+    return 0;
+}
+
+static inline int64_t wrap(int64_t a, int64_t n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+static inline int64_t neighbour(const orc_params *P, int64_t x, int64_t y, int64_t z, const int *e) {
+    int64_t X = wrap(x + e[0], P->nx), Y = wrap(y + e[1], P->ny), Z = wrap(z + e[2], P->nz);
+    return X + P->nx * (Y + P->ny * Z);
+}
+
+static double psi_of(const orc_params *P, double rho) {
+    return P->psi == 1 ? 1.0 - exp(-rho) : rho;
+}
+
+/* Shan-Chen interaction force on component c at node (x,y,z) (Shan-Chen
+ * subsection): -G psi_c(x) sum_i w_i psi_other(x + e_i) e_i, plus rho_c g. */
+static void sc_force(const orc_params *P, const lattice_t *L, const double *psi, int64_t N,
+                     int64_t x, int64_t y, int64_t z, int c, double rho_c, double *F) {
+    int64_t n = x + P->nx * (y + P->ny * z);
+    const double *po = psi + (1 - c) * N;
+    double s[3] = {0, 0, 0};
+    for (int i = 0; i < L->q; i++) {
+        double pn = po[neighbour(P, x, y, z, L->e[i])];
+        for (int a = 0; a < 3; a++) s[a] += L->w[i] * pn * L->e[i][a];
+    }
+    for (int a = 0; a < 3; a++) F[a] = -P->G * psi[c * N + n] * s[a] + rho_c * P->g[a];
+}
+
+int orc_init_eq(const orc_params *P, const double *rho, const double *u, const double *df, double *f) {
+    if (check_params(P)) return -1;
+    lattice_t L;
+    make_lattice(P->lattice, &L);
+    int64_t N = (int64_t)P->nx * P->ny * P->nz;
+    int C = P->model == ORC_SHANCHEN ? 2 : 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++) {
+        double uu[3] = {0, 0, 0}, feq[QMAX];
+        for (int a = 0; a < L.d; a++) uu[a] = u[a * N + n];
+        for (int c = 0; c < C; c++) {
+            if (P->model == ORC_ELBM) feq_entropic(&L, rho[c * N + n], uu, feq);
+            else feq_poly(&L, rho[c * N + n], uu, feq);
+            for (int i = 0; i < L.q; i++) {
+                int64_t k = ((int64_t)c * L.q + i) * N + n;
+                f[k] = feq[i] + (df ? df[k] : 0.0);
+            }
+        }
+    }
+    return 0;
+}
+
+int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc_stats *st) {
+    if (check_params(P) || steps < 0) return -1;
+    lattice_t L;
+    make_lattice(P->lattice, &L);
+    const int q = L.q;
+    const int64_t N = (int64_t)P->nx * P->ny * P->nz;
+    const int C = P->model == ORC_SHANCHEN ? 2 : 1;
+    if (C == 2 && flags)
+        for (int64_t n = 0; n < N; n++)
+            if (flags[n]) return -2; /* walls are not defined for the two-component model */
+    double *cur = f;
+    double *nxt = (double *)malloc(sizeof(double) * C * q * N);
+    double *rho_all = C == 2 ? (double *)malloc(sizeof(double) * 2 * N) : NULL;
+    double *psi = C == 2 ? (double *)malloc(sizeof(double) * 2 * N) : NULL;
+    if (!nxt || (C == 2 && (!rho_all || !psi))) {
+        free(nxt);
+        free(rho_all);
+        free(psi);
+        return -3;
+    }
+    int64_t hist[32] = {0}, noconv = 0, nodes = 0;
+
+    for (int t = 0; t < steps; t++) {
+        if (C == 2) {
+            /* macroscopic pre-pass: every node's density and pseudopotential at time t */
+#pragma omp parallel for schedule(static)
+            for (int64_t n = 0; n < N; n++)
+                for (int c = 0; c < 2; c++) {
+                    double r = 0.0;
+                    for (int i = 0; i < q; i++) r += cur[((int64_t)c * q + i) * N + n];
+                    rho_all[c * N + n] = r;
+                    psi[c * N + n] = psi_of(P, r);
+                }
+        }
+#pragma omp parallel for schedule(static) reduction(+ : noconv, nodes)
+        for (int64_t n = 0; n < N; n++) {
+            int64_t x = n % P->nx, y = (n / P->nx) % P->ny, z = n / ((int64_t)P->nx * P->ny);
+            double fl[2][QMAX], post[2][QMAX];
+            for (int c = 0; c < C; c++)
+                for (int i = 0; i < q; i++) fl[c][i] = cur[((int64_t)c * q + i) * N + n];
+            if (flags && flags[n] == 1) {
+                /* full-way bounce-back: a wall node returns each population along the
+                 * opposite direction instead of colliding */
+                for (int c = 0; c < C; c++)
+                    for (int i = 0; i < q; i++) post[c][i] = fl[c][L.opp[i]];
+            } else if (C == 1) {
+                node_info info = {0, 1};
+                collide_single(P, &L, fl[0], post[0], &info);
+                if (P->model == ORC_ELBM) {
+                    int b = info.iters < 31 ? info.iters : 31;
+#pragma omp atomic
+                    hist[b]++;
+                    noconv += !info.converged;
+                    nodes++;
+                }
+            } else {
+                /* Shan-Chen with EDM forcing around the common velocity */
+                double rc[2], jc[2][3], Fc[2][3], up[3], num[3] = {0, 0, 0}, den = 0.0;
+                for (int c = 0; c < 2; c++) {
+                    moments(&L, fl[c], &rc[c], jc[c]);
+                    sc_force(P, &L, psi, N, x, y, z, c, rc[c], Fc[c]);
+                    for (int a = 0; a < 3; a++) num[a] += jc[c][a] / P->tau;
+                    den += rc[c] / P->tau;
+                }
+                for (int a = 0; a < 3; a++) up[a] = num[a] / den;
+                for (int c = 0; c < 2; c++) {
+                    double f0[QMAX], f1[QMAX], u1[3];
+                    for (int a = 0; a < 3; a++) u1[a] = up[a] + Fc[c][a] / rc[c];
+                    feq_poly(&L, rc[c], up, f0);
+                    feq_poly(&L, rc[c], u1, f1);
+                    for (int i = 0; i < q; i++)
+                        post[c][i] = fl[c][i] + (f0[i] - fl[c][i]) / P->tau + (f1[i] - f0[i]);
+                }
+            }
+            /* propagation: the value leaving node x along e_i lands on x + e_i */
+            for (int i = 0; i < q; i++) {
+                int64_t dst = neighbour(P, x, y, z, L.e[i]);
+                for (int c = 0; c < C; c++) nxt[((int64_t)c * q + i) * N + dst] = post[c][i];
+            }
+        }
+        double *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    if (cur != f) {
+        memcpy(f, cur, sizeof(double) * C * q * N);
+        nxt = cur;
+    }
+    free(nxt);
+    free(rho_all);
+    free(psi);
+    if (st) {
+        for (int b = 0; b < 32; b++) st->newton_hist[b] += hist[b];
+        st->nonconverged += noconv;
+        st->nodes += nodes;
+    }
+    return 0;
+}
+
+int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double *rho, double *u) {
+    if (check_params(P)) return -1;
+    lattice_t L;
+    make_lattice(P->lattice, &L);
+    const int q = L.q;
+    const int64_t N = (int64_t)P->nx * P->ny * P->nz;
+    const int C = P->model == ORC_SHANCHEN ? 2 : 1;
+    double *psi = NULL;
+    if (C == 2) {
+        psi = (double *)malloc(sizeof(double) * 2 * N);
+        if (!psi) return -3;
+        for (int64_t n = 0; n < N; n++)
+            for (int c = 0; c < 2; c++) {
+                double r = 0.0;
+                for (int i = 0; i < q; i++) r += f[((int64_t)c * q + i) * N + n];
+                psi[c * N + n] = psi_of(P, r);
+            }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; n++) {
+        int64_t x = n % P->nx, y = (n / P->nx) % P->ny, z = n / ((int64_t)P->nx * P->ny);
+        double rc[2], jc[2][3], fl[QMAX];
+        for (int c = 0; c < C; c++) {
+            for (int i = 0; i < q; i++) fl[i] = f[((int64_t)c * q + i) * N + n];
+            moments(&L, fl, &rc[c], jc[c]);
+            rho[c * N + n] = rc[c];
+        }
+        double v[3] = {0, 0, 0};
+        if (!(flags && flags[n] == 1)) {
+            if (C == 1) {
+                double gfac = P->model == ORC_ELBM ? 0.0 : 0.5;
+                for (int a = 0; a < 3; a++) v[a] = (jc[0][a] + gfac * rc[0] * P->g[a]) / rc[0];
+            } else {
+                /* mixture velocity (sum_c j_c + F_total/2) / sum_c rho_c */
+                double Fc[3], num[3] = {jc[0][0] + jc[1][0], jc[0][1] + jc[1][1], jc[0][2] + jc[1][2]};
+                for (int c = 0; c < 2; c++) {
+                    sc_force(P, &L, psi, N, x, y, z, c, rc[c], Fc);
+                    for (int a = 0; a < 3; a++) num[a] += 0.5 * Fc[a];
+                }
+                for (int a = 0; a < 3; a++) v[a] = num[a] / (rc[0] + rc[1]);
+            }
+        }
+        for (int a = 0; a < 3; a++) u[a * N + n] = v[a];
+    }
+    free(psi);
+    return 0;
+}

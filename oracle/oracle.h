@@ -1,0 +1,75 @@
+/*
+ * FP64 CPU oracle for the fused lattice Boltzmann stream-and-collide step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow reference that
+ * the HIP path is checked against.  Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load it.  It shares no code, header,
+ * table or helper with the HIP library: its lattice tables are typed in here
+ * from the paper's weight table and the velocity ordering documented below.
+ *
+ * Velocity ordering (opposite pairs adjacent, opp(i) = i+1 for odd i):
+ *   D2Q9 : 0 (0,0) 1 (1,0) 2 (-1,0) 3 (0,1) 4 (0,-1) 5 (1,1) 6 (-1,-1) 7 (-1,1) 8 (1,-1)
+ *   D3Q19: 0 rest, 1/2 +-x, 3/4 +-y, 5/6 +-z, 7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0)
+ *          11 (1,0,1) 12 (-1,0,-1) 13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1) 16 (0,-1,-1)
+ *          17 (0,1,-1) 18 (0,-1,1)
+ *
+ * Array layouts: populations f[C][Q][N], N = nx*ny*nz with x fastest
+ * (node n = x + nx*(y + ny*z)); flags[N] (0 fluid, 1 full-way bounce-back wall);
+ * densities rho[C][N]; velocities u[3][N] (the z row is zero on D2Q9).
+ *
+ * Parity unpinned (no printed values in the paper): the MRT, ELBM and
+ * Shan-Chen steps beyond the identities and closed forms the tests check.
+ */
+#ifndef LBM_ORACLE_H
+#define LBM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
+enum { ORC_BGK = 0, ORC_MRT = 1, ORC_ELBM = 2, ORC_SHANCHEN = 3 };
+
+typedef struct {
+    int lattice, model;
+    int nx, ny, nz;
+    double tau;
+    double g[3];          /* body acceleration; the force density is rho*g */
+    double s[19];         /* MRT rates, moment order (see orc_mrt_matrix) */
+    int alpha_init;       /* ELBM first guess: 0 -> 2, 1 -> series, 2 -> MLP */
+    double alpha_tol;     /* Newton stop |d alpha| <= tol */
+    int alpha_maxit;
+    const double *mlp;    /* 1313 MLP parameters (alpha_init == 2) */
+    double G;             /* Shan-Chen coupling */
+    int psi;              /* 0: psi = rho, 1: psi = 1 - exp(-rho) */
+} orc_params;
+
+typedef struct {
+    int64_t newton_hist[32];  /* ELBM nodes by Newton iteration count (0 = short-cut) */
+    int64_t nonconverged;
+    int64_t nodes;
+} orc_stats;
+
+int orc_q(int lattice);
+void orc_tables(int lattice, int *e /* q*3 */, double *w, int *opp);
+void orc_feq(int lattice, double rho, const double *u, double *feq);
+void orc_feq_entropic(int lattice, double rho, const double *u, double *feq);
+void orc_mrt_matrix(int lattice, double *M /* q*q row-major */);
+double orc_H(int lattice, const double *f);
+double orc_alpha(int lattice, const double *f, const double *feq, int init, const double *mlp,
+                 double vsq, double tol, int maxit, int *iters, int *converged);
+void orc_alpha_features(int lattice, const double *f, const double *feq, double rho, double vsq,
+                        double *feat /* 6 */);
+void orc_mlp_forward(const double *p, const double *x, int64_t n, double *y);
+double orc_mlp_loss_grad(const double *p, const double *x, const double *t, int64_t n, double *grad);
+void orc_collide_node(const orc_params *P, const double *f, double *out);
+int orc_init_eq(const orc_params *P, const double *rho, const double *u, const double *df, double *f);
+int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc_stats *st);
+int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double *rho, double *u);
+int orc_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
