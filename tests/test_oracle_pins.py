@@ -528,6 +528,27 @@ def test_shan_chen_force_closed_form():
     assert np.abs(u[1:]).max() < 1e-16
 
 
+def test_shan_chen_component_momentum_closed_form():
+    """rho_A = 1 + eps cos(kx), rho_B = 1 + eps sin(kx) at rest: after one step
+    component A carries the domain sum of its force, -G (1/3) eps^2 sin(k) n/2
+    per (y, z) line, and B the opposite; a body force g adds rho_c g per node
+    (EDM forcing delivers exactly F to each component's momentum)."""
+    n, eps, G, g = 16, 1e-2, 0.8, 3e-5
+    k = 2 * np.pi / n
+    x = np.tile(np.arange(n, dtype=float), 4)
+    rho = np.vstack([1 + eps * np.cos(k * x), 1 + eps * np.sin(k * x)])
+    e, _, _ = oracle.tables(S.D3Q19)
+    for gx in (0.0, g):
+        o = oracle.Oracle(S.D3Q19, S.SHANCHEN, n, 2, 2, 0.9, (gx, 0, 0), G=G)
+        o.init_eq(rho, np.zeros((3, 4 * n)))
+        o.run(1)
+        pA, pB = (np.einsum("qn,qa->a", o.f[c], e) for c in (0, 1))
+        sc = G / 3 * eps ** 2 * np.sin(k) * n / 2 * 4
+        np.testing.assert_allclose(pA[0], -sc + gx * rho[0].sum(), rtol=1e-11)
+        np.testing.assert_allclose(pB[0], sc + gx * rho[1].sum(), rtol=1e-11)
+        assert np.abs(pA[1:]).max() < 1e-16 and np.abs(pB[1:]).max() < 1e-16
+
+
 # --------------------------------------------------------------------------- MLP
 
 def test_mlp_gradient_matches_central_differences():
