@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Throughput of the fused LBM stream-and-collide step on one MI355X.
+
+Workload (synthetic, shaped like the paper's periodic vortex benchmarks): D3Q19 LBGK,
+3-D Taylor-Green vortex on a 256^3 periodic lattice, u0 = 0.04, nu = 0.01, rho = 1, plus
+seeded U(+-1e-6) noise on every population.  A step is one fused stream-and-collide
+kernel over all 16.8 M nodes (inputs resident in HBM).
+
+Prints ONE JSON line: MLUPS of the FP32 run (``value``), the roofline of the step
+kernel (algorithmic bytes / measured kernel time vs 8 TB/s), the shifted BF16/F16/FP32
+storage variants with their MLUPS and velocity error after 1000 steps, and the FP64
+oracle timed on the host cores (``cpu_baseline``).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_SIDE = 256
+ERR_STEPS = 1000
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1311_2404_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel_tag, per_launch_nodes):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, only if they were
+    taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_tag)
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def bytes_per_node(storage):
+    from paper_1311_2404_amd import ELEM_BYTES
+    return 2 * 19 * ELEM_BYTES[storage]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--layout", choices=["ab", "aa"], default="ab")
+    ap.add_argument("--n", type=int, default=N_SIDE, help="lattice side (default 256)")
+    ap.add_argument("--no-variants", action="store_true", help="time the FP32 run only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1311_2404_amd as P
+    import synthetic as S
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    layout = P.LBM_AA if args.layout == "aa" else P.LBM_AB
+    n = args.n
+    N = n ** 3
+    case = S.c2_taylor_green(n=n, steps=ERR_STEPS)
+    print("[bench] inputs ready: D3Q19 BGK TGV %d^3" % n, file=sys.stderr, flush=True)
+
+    def make(storage):
+        s = P.Sim.from_case(case, storage, layout, stream=stream)
+        return s
+
+    def timed(storage, steps, warmup):
+        s = make(storage)
+        s.step(warmup)
+        s.sync()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        s.step(steps)
+        e1.record(stream)
+        s.sync()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kern_ms = e0.elapsed_time(e1) / steps
+        s.close()
+        return wall, kern_ms
+
+    # headline: FP32 storage
+    wall, kern_ms = timed(P.LBM_F32, args.steps, args.warmup)
+    mlups = N * args.steps / wall / 1e6
+    bpn = bytes_per_node(P.LBM_F32)
+    achieved = bpn * N / (kern_ms * 1e-3) / 1e9
+    print("[bench] fp32: %.1f MLUPS, %.4f ms/step" % (mlups, wall / args.steps * 1e3), file=sys.stderr, flush=True)
+
+    # velocity error after the configuration's 1000 steps, vs the FP64 run of the same kernel
+    # (which matches the FP64 oracle to 1e-12 in the parity tests) and vs the Navier-Stokes KE law
+    def run_fields(storage):
+        s = make(storage)
+        s.step(ERR_STEPS)
+        rho, u = s.macro()
+        s.close()
+        return u
+
+    u64 = run_fields(P.LBM_F64)
+    k = 2 * np.pi / n
+    ke_law = float(np.exp(-6 * case.extra["nu"] * k * k * ERR_STEPS))
+    ke0 = float((case.u ** 2).sum())
+
+    def errs(u):
+        return {"vel_rel_l2_vs_fp64": float(np.linalg.norm(u - u64) / np.linalg.norm(u64)),
+                "ke_ratio": float((u ** 2).sum() / ke0), "ke_ratio_ns_law": ke_law}
+
+    variants = {"f32": dict(mlups=round(mlups, 1), bytes_per_node=bpn, **errs(run_fields(P.LBM_F32)))}
+    if not args.no_variants:
+        for st in (P.LBM_F32S, P.LBM_BF16S, P.LBM_F16S, P.LBM_F64):
+            w2, k2 = timed(st, args.steps, args.warmup)
+            m2 = N * args.steps / w2 / 1e6
+            b2 = bytes_per_node(st)
+            v = dict(mlups=round(m2, 1), bytes_per_node=b2,
+                     hbm_gbs_algorithmic=round(b2 * N / (k2 * 1e-3) / 1e9, 1))
+            if st != P.LBM_F64:
+                v.update(errs(run_fields(st)))
+            variants[P.STORAGE_NAMES[st]] = v
+            print("[bench] %s: %.1f MLUPS" % (P.STORAGE_NAMES[st], m2), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.Oracle.from_case(case)
+        o.run(1)  # first touch of the second copy
+        t0 = time.perf_counter()
+        o.run(args.cpu_steps)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(N * args.cpu_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": "FP64 oracle, the same 256^3 D3Q19 BGK Taylor-Green state, %d steps (%.1f s)"
+                         % (args.cpu_steps, dt)}
+
+    tag = "d3q19_bgk_f32_%s_%d" % (args.layout, n)
+    traffic = stored_traffic(tag, N)
+    out = {
+        "metric": "MLUPS and % of HBM roofline, D3Q19 256^3 FP32 vs shifted-BF16 at stated error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D3Q19 LBGK 3-D Taylor-Green vortex %d^3 periodic, u0=0.04, nu=0.01, "
+                               "+-1e-6 seeded noise, FP32 storage, %s streaming" % (n, args.layout.upper()),
+                   "nodes": N, "layout": args.layout},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_step<D3Q19, F32, BGK>", "bytes_per_node": bpn,
+                     "kernel_ms_per_launch": round(kern_ms, 5)},
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

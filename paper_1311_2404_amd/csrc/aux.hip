@@ -1,0 +1,251 @@
+// Auxiliary kernels: equilibrium initialisation, population plane transfer in the
+// canonical (physical) layout, macroscopic output and deterministic FP64 diagnostics.
+#include "dispatch.hpp"
+#include "step.hpp"
+
+namespace lbm {
+
+namespace {
+
+dim3 flat_grid(uint32_t N, int bs) { return dim3((N + bs - 1) / bs); }
+
+__device__ __forceinline__ Geo geo_of(uint32_t n, int nx, int ny, int nz) {
+    const int x = int(n % uint32_t(nx));
+    const int y = int((n / uint32_t(nx)) % uint32_t(ny));
+    const int z = int(n / (uint32_t(nx) * uint32_t(ny)));
+    return make_geo(x, y, z, nx, ny, nz);
+}
+
+// f_eq(rho, u)_i - w_i in FP64: the polynomial equilibrium of section 2, or the entropic one.
+template <class L>
+__device__ double heq_plane(int q, double rho, double ux, double uy, double uz, int entropic) {
+    if (entropic) {
+        double heq[L::Q];
+        entropic_heq<L, double>(rho - 1.0, rho, ux, uy, uz, heq);
+        double r = heq[0];
+#pragma unroll
+        for (int i = 1; i < L::Q; i++)
+            if (i == q) r = heq[i];
+        return r;
+    }
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        if (i != q) continue;
+        const double eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
+        const double usq = ux * ux + uy * uy + uz * uz;
+        r = L::w(i) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+    }
+    return r;
+}
+
+template <class L>
+__device__ __forceinline__ void canon_loc_rt(int layout, int q, const Geo &g, int &slot, uint32_t &node) {
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+        if (i == q) canon_loc<L>(layout, i, g, slot, node);
+}
+
+template <class L, class St>
+__global__ void k_init_plane(PlaneParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    const Geo g = geo_of(n, p.nx, p.ny, p.nz);
+    const double ux = p.u[n], uy = p.u[p.N + n], uz = L::D == 3 ? p.u[2 * size_t(p.N) + n] : 0.0;
+    double h = heq_plane<L>(p.q, p.rho[n], ux, uy, uz, p.entropic);
+    if (p.df) h += p.df[n];
+    int slot;
+    uint32_t nd;
+    canon_loc_rt<L>(p.layout, p.q, g, slot, nd);
+    double w = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+        if (i == p.q) w = L::w(i);
+    T *pop = static_cast<T *>(p.pop) + size_t(p.comp) * L::Q * p.N;
+    // unshifted storages round f = w + h once; shifted ones round h
+    if constexpr (St::shifted) pop[size_t(slot) * p.N + nd] = St::encode(C(h), C(w), 0u);
+    else pop[size_t(slot) * p.N + nd] = T(w + h);
+}
+
+template <class L, class St>
+__global__ void k_get_plane(PlaneParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    const Geo g = geo_of(n, p.nx, p.ny, p.nz);
+    int slot;
+    uint32_t nd;
+    canon_loc_rt<L>(p.layout, p.q, g, slot, nd);
+    double w = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+        if (i == p.q) w = L::w(i);
+    const T *pop = static_cast<const T *>(p.pop) + size_t(p.comp) * L::Q * p.N;
+    const T v = pop[size_t(slot) * p.N + nd];
+    if constexpr (St::shifted) p.plane[n] = w + double(St::decode(v, C(w)));
+    else p.plane[n] = double(v);
+}
+
+template <class L, class St>
+__global__ void k_set_plane(PlaneParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    const Geo g = geo_of(n, p.nx, p.ny, p.nz);
+    int slot;
+    uint32_t nd;
+    canon_loc_rt<L>(p.layout, p.q, g, slot, nd);
+    double w = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+        if (i == p.q) w = L::w(i);
+    T *pop = static_cast<T *>(p.pop) + size_t(p.comp) * L::Q * p.N;
+    if constexpr (St::shifted) pop[size_t(slot) * p.N + nd] = St::encode(C(p.plane[n] - w), C(w), 0u);
+    else pop[size_t(slot) * p.N + nd] = T(p.plane[n]);
+}
+
+// Macroscopic output.  Density per component; velocity (j + F/2)/rho for the forced
+// single-component models, j/rho for ELBM, the mixture velocity for Shan-Chen; 0 on walls.
+template <class L, class St>
+__global__ void k_macro(MacroParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    const Geo g = geo_of(n, p.nx, p.ny, p.nz);
+    double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < p.ncomp; c++) {
+        const T *pop = static_cast<const T *>(p.pop) + size_t(c) * L::Q * p.N;
+        C h[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            int slot;
+            uint32_t nd;
+            canon_loc<L>(p.layout, i, g, slot, nd);
+            h[i] = St::decode(pop[size_t(slot) * p.N + nd], C(L::w(i)));
+        }
+        const Macro<C> m = moments<L, C>(h);
+        rho[c] = double(m.rho);
+        j[0] += double(m.jx);
+        j[1] += double(m.jy);
+        j[2] += double(m.jz);
+    }
+    const double rt = rho[0] + rho[1];
+    double v[3] = {0.0, 0.0, 0.0};
+    const bool wall = p.flags && p.flags[n] == 1;
+    if (!wall) {
+        if (p.model == M_SC) {
+            const C *psi = static_cast<const C *>(p.psi);
+            double F[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 2; c++) {
+                const C *po = psi + size_t(1 - c) * p.N;
+                double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 1; i < L::Q; i++) {
+                    const double pv = L::w(i) * double(po[g.at(L::ex(i), L::ey(i), L::ez(i))]);
+                    s[0] += L::ex(i) * pv;
+                    s[1] += L::ey(i) * pv;
+                    s[2] += L::ez(i) * pv;
+                }
+                const double a = -p.G * double(psi[size_t(c) * p.N + n]);
+                for (int k = 0; k < 3; k++) F[k] += a * s[k] + rho[c] * p.g[k];
+            }
+            for (int k = 0; k < 3; k++) v[k] = (j[k] + 0.5 * F[k]) / rt;
+        } else {
+            const double hf = p.model == M_ELBM ? 0.0 : 0.5;
+            for (int k = 0; k < 3; k++) v[k] = (j[k] + hf * rho[0] * p.g[k]) / rho[0];
+        }
+    }
+    if (p.bad) {
+        bool ok = true;
+        for (int c = 0; c < p.ncomp; c++) ok = ok && (rho[c] > 0.0) && isfinite(rho[c]);
+        if (!ok) atomicAdd(p.bad, 1u);
+    }
+    if (p.fp64) {
+        double *ro = static_cast<double *>(p.rho_out), *uo = static_cast<double *>(p.u_out);
+        for (int c = 0; c < p.ncomp; c++) ro[size_t(c) * p.N + n] = rho[c];
+        for (int k = 0; k < 3; k++) uo[size_t(k) * p.N + n] = v[k];
+    } else {
+        float *ro = static_cast<float *>(p.rho_out), *uo = static_cast<float *>(p.u_out);
+        for (int c = 0; c < p.ncomp; c++) ro[size_t(c) * p.N + n] = float(rho[c]);
+        for (int k = 0; k < 3; k++) uo[size_t(k) * p.N + n] = float(v[k]);
+    }
+}
+
+constexpr int RED_BS = 256;
+constexpr int RED_K = 8;  // mass0, mass1, px, py, pz, ke, bad, (unused)
+
+// Per-block partial sums in a fixed order (grid-stride over nodes, tree in LDS).
+__global__ __launch_bounds__(RED_BS) void k_diag_partials(const double *rho, const double *u, uint32_t N, int ncomp,
+                                                          double *partials) {
+    __shared__ double s[RED_K][RED_BS];
+    double acc[RED_K] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t n = blockIdx.x * RED_BS + threadIdx.x; n < N; n += gridDim.x * RED_BS) {
+        const double r0 = rho[n], r1 = ncomp == 2 ? rho[size_t(N) + n] : 0.0;
+        const double ux = u[n], uy = u[size_t(N) + n], uz = u[2 * size_t(N) + n];
+        const double rt = r0 + r1;
+        acc[0] += r0;
+        acc[1] += r1;
+        acc[2] += rt * ux;
+        acc[3] += rt * uy;
+        acc[4] += rt * uz;
+        acc[5] += ux * ux + uy * uy + uz * uz;
+        bool ok = (r0 > 0.0) && isfinite(r0) && (ncomp == 1 || ((r1 > 0.0) && isfinite(r1)));
+        acc[6] += ok ? 0.0 : 1.0;
+    }
+    for (int k = 0; k < RED_K; k++) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = RED_BS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < RED_K; k++) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < RED_K) partials[size_t(blockIdx.x) * RED_K + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_diag_final(const double *partials, int nblocks, uint32_t N, double *out) {
+    const int k = threadIdx.x;
+    if (k >= RED_K) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; b++) acc += partials[size_t(b) * RED_K + k];
+    if (k == 5) acc *= 0.5 / double(N);
+    out[k] = acc;
+}
+
+}  // namespace
+
+#define LBM_AUX_LAUNCH(KERNEL, P)                                                          \
+    return with_lattice(lattice, [&](auto lt) {                                            \
+        using L = decltype(lt);                                                            \
+        return with_storage<false>(storage, 0, [&](auto st) {                              \
+            using St = decltype(st);                                                       \
+            KERNEL<L, St><<<flat_grid(P.N, 256), 256, 0, c.stream>>>(P);                   \
+            return hipGetLastError();                                                      \
+        });                                                                                \
+    })
+
+hipError_t launch_init_plane(int lattice, int storage, const PlaneParams &p, const LaunchCfg &c) {
+    LBM_AUX_LAUNCH(k_init_plane, p);
+}
+hipError_t launch_get_plane(int lattice, int storage, const PlaneParams &p, const LaunchCfg &c) {
+    LBM_AUX_LAUNCH(k_get_plane, p);
+}
+hipError_t launch_set_plane(int lattice, int storage, const PlaneParams &p, const LaunchCfg &c) {
+    LBM_AUX_LAUNCH(k_set_plane, p);
+}
+hipError_t launch_macro(int lattice, int storage, const MacroParams &p, const LaunchCfg &c) {
+    LBM_AUX_LAUNCH(k_macro, p);
+}
+
+hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, int ncomp, double *partials,
+                              int nblocks, double *out, hipStream_t s) {
+    k_diag_partials<<<nblocks, RED_BS, 0, s>>>(rho, u, N, ncomp, partials);
+    k_diag_final<<<1, 64, 0, s>>>(partials, nblocks, N, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,394 @@
+// Per-node collision operators of the fused step, in shifted space h_i = f_i - w_i.
+//
+//   BGK : h* = h + omega (heq - h) + (1 - omega/2) w_i [3(e_i - v) + 9 (e_i.v) e_i].F
+//         (LBGK with the relaxation sign of the paper's GPU step algorithm, polynomial
+//         equilibrium of section 2, Guo forcing of the body-forces subsection,
+//         v = (j + F/2)/rho, F = rho g)
+//   MRT : m* = m - S (m - m_eq) + (I - S/2) M F~ in the orthogonal moment basis of
+//         d'Humieres et al. (2002), cited by the MRT subsection; transforms written with
+//         pair sums/differences, equilibrium and source moments in closed form
+//   ELBM: h* = h + alpha beta (heq - h), beta = 1/(2 tau), heq the discrete entropic
+//         equilibrium, alpha the nontrivial root of H(f + alpha (feq - f)) = H(f)
+//         (entropic LBM subsection), solved in FP64
+//   SC  : two components, force -G psi_c(x) sum_i w_i psi_other(x+e_i) e_i (Shan-Chen
+//         subsection), common velocity, exact-difference-method forcing
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lattice.hpp"
+#include "params.hpp"
+
+namespace lbm {
+
+template <class C>
+struct Macro {
+    C drho, rho, jx, jy, jz;
+};
+
+template <class L, class C>
+__device__ __forceinline__ Macro<C> moments(const C *h) {
+    Macro<C> m;
+    C r = h[0], jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+        r += h[i];
+        if (L::ex(i) == 1) jx += h[i];
+        if (L::ex(i) == -1) jx -= h[i];
+        if (L::ey(i) == 1) jy += h[i];
+        if (L::ey(i) == -1) jy -= h[i];
+        if (L::ez(i) == 1) jz += h[i];
+        if (L::ez(i) == -1) jz -= h[i];
+    }
+    m.drho = r;
+    m.rho = C(1) + r;
+    m.jx = jx;
+    m.jy = jy;
+    m.jz = jz;
+    return m;
+}
+
+template <class L>
+__device__ __forceinline__ constexpr int edot(int i, int a, int b, int c) {
+    return L::ex(i) * a + L::ey(i) * b + L::ez(i) * c;
+}
+
+// ---------------------------------------------------------------------------- BGK
+template <class L, class C>
+__device__ __forceinline__ void collide_bgk(const C *h, C *o, const StepParams &p) {
+    const Macro<C> m = moments<L, C>(h);
+    const C omega = C(p.omega);
+    const C irho = C(1) / m.rho;
+    C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
+    C Fx = C(0), Fy = C(0), Fz = C(0);
+    if (p.has_force) {
+        const C gx = C(p.g[0]), gy = C(p.g[1]), gz = C(L::D == 3 ? p.g[2] : 0.0);
+        vx += C(0.5) * gx;
+        vy += C(0.5) * gy;
+        vz += C(0.5) * gz;
+        Fx = m.rho * gx;
+        Fy = m.rho * gy;
+        Fz = m.rho * gz;
+    }
+    const C usq15 = C(1.5) * (vx * vx + vy * vy + vz * vz);
+    const C pre = C(1) - C(0.5) * omega;
+    const C vF = vx * Fx + vy * Fy + vz * Fz;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const C w = C(L::w(i));
+        const C eu = C(L::ex(i)) * vx + C(L::ey(i)) * vy + C(L::ez(i)) * vz;
+        const C heq = w * (m.drho + m.rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
+        C r = h[i] + omega * (heq - h[i]);
+        if (p.has_force) {
+            const C eF = C(L::ex(i)) * Fx + C(L::ey(i)) * Fy + C(L::ez(i)) * Fz;
+            r += pre * w * (C(3) * (eF - vF) + C(9) * eu * eF);
+        }
+        o[i] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------- MRT
+// D3Q19 basis rows (q = |e|^2): 1, 19q-30, (21q^2-53q+24)/2, ex, (5q-9)ex, ey,
+// (5q-9)ey, ez, (5q-9)ez, 3ex^2-q, (3q-5)(3ex^2-q), ey^2-ez^2, (3q-5)(ey^2-ez^2),
+// exey, eyez, exez, (ey^2-ez^2)ex, (ez^2-ex^2)ey, (ex^2-ey^2)ez; squared norms
+// 19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8.
+template <class C>
+__device__ __forceinline__ void collide_mrt_d3q19(const C *h, C *o, const StepParams &p) {
+    // pair sums and differences (opposite directions are adjacent)
+    const C s1 = h[1] + h[2], d1 = h[1] - h[2];
+    const C s3 = h[3] + h[4], d3 = h[3] - h[4];
+    const C s5 = h[5] + h[6], d5 = h[5] - h[6];
+    const C s7 = h[7] + h[8], d7 = h[7] - h[8];
+    const C s9 = h[9] + h[10], d9 = h[9] - h[10];
+    const C s11 = h[11] + h[12], d11 = h[11] - h[12];
+    const C s13 = h[13] + h[14], d13 = h[13] - h[14];
+    const C s15 = h[15] + h[16], d15 = h[15] - h[16];
+    const C s17 = h[17] + h[18], d17 = h[17] - h[18];
+    const C Sa = s1 + s3 + s5;
+    const C Sxy = s7 + s9, Sxz = s11 + s13, Syz = s15 + s17;
+    const C Sd = Sxy + Sxz + Syz;
+
+    const C drho = h[0] + Sa + Sd;
+    const C jx = d1 + d7 + d9 + d11 + d13;
+    const C jy = d3 + d7 - d9 + d15 + d17;
+    const C jz = d5 + d11 - d13 + d15 - d17;
+    C m[19];
+    m[1] = C(-30) * h[0] - C(11) * Sa + C(8) * Sd;
+    m[2] = C(12) * h[0] - C(4) * Sa + Sd;
+    m[4] = C(-4) * d1 + d7 + d9 + d11 + d13;
+    m[6] = C(-4) * d3 + d7 - d9 + d15 + d17;
+    m[8] = C(-4) * d5 + d11 - d13 + d15 - d17;
+    m[9] = C(2) * s1 - s3 - s5 + Sxy + Sxz - C(2) * Syz;
+    m[10] = C(-4) * s1 + C(2) * (s3 + s5) + Sxy + Sxz - C(2) * Syz;
+    m[11] = s3 - s5 + Sxy - Sxz;
+    m[12] = C(-2) * s3 + C(2) * s5 + Sxy - Sxz;
+    m[13] = s7 - s9;
+    m[14] = s15 - s17;
+    m[15] = s11 - s13;
+    m[16] = d7 + d9 - d11 - d13;
+    m[17] = -d7 + d9 + d15 + d17;
+    m[18] = d11 - d13 - d15 + d17;
+
+    const C rho = C(1) + drho;
+    const C irho = C(1) / rho;
+    C vx = jx * irho, vy = jy * irho, vz = jz * irho;
+    C Fx = C(0), Fy = C(0), Fz = C(0);
+    if (p.has_force) {
+        vx += C(0.5) * C(p.g[0]);
+        vy += C(0.5) * C(p.g[1]);
+        vz += C(0.5) * C(p.g[2]);
+        Fx = rho * C(p.g[0]);
+        Fy = rho * C(p.g[1]);
+        Fz = rho * C(p.g[2]);
+    }
+    const C vsq = vx * vx + vy * vy + vz * vz;
+    // equilibrium moments of the polynomial equilibrium at (rho, v), shifted space
+    C meq[19], mf[19];
+    meq[1] = C(-11) * drho + C(19) * rho * vsq;
+    meq[2] = C(3) * drho - C(5.5) * rho * vsq;
+    meq[4] = C(-2.0 / 3.0) * rho * vx;
+    meq[6] = C(-2.0 / 3.0) * rho * vy;
+    meq[8] = C(-2.0 / 3.0) * rho * vz;
+    meq[9] = rho * (C(2) * vx * vx - vy * vy - vz * vz);
+    meq[10] = C(-0.5) * meq[9];
+    meq[11] = rho * (vy * vy - vz * vz);
+    meq[12] = C(-0.5) * meq[11];
+    meq[13] = rho * vx * vy;
+    meq[14] = rho * vy * vz;
+    meq[15] = rho * vx * vz;
+    meq[16] = meq[17] = meq[18] = C(0);
+    // moments of the Guo source: the derivative of m_eq along F
+    const C vF = vx * Fx + vy * Fy + vz * Fz;
+    mf[1] = C(38) * vF;
+    mf[2] = C(-11) * vF;
+    mf[4] = C(-2.0 / 3.0) * Fx;
+    mf[6] = C(-2.0 / 3.0) * Fy;
+    mf[8] = C(-2.0 / 3.0) * Fz;
+    mf[9] = C(2) * (C(2) * vx * Fx - vy * Fy - vz * Fz);
+    mf[10] = C(-0.5) * mf[9];
+    mf[11] = C(2) * (vy * Fy - vz * Fz);
+    mf[12] = C(-0.5) * mf[11];
+    mf[13] = vx * Fy + vy * Fx;
+    mf[14] = vy * Fz + vz * Fy;
+    mf[15] = vx * Fz + vz * Fx;
+    mf[16] = mf[17] = mf[18] = C(0);
+
+    // relax; conserved rows: rho unchanged, j gains F whatever their rate
+    const C n2[19] = {C(19), C(2394), C(252), C(10), C(40), C(10), C(40), C(10), C(40), C(36),
+                      C(72), C(12), C(24), C(4), C(4), C(4), C(8), C(8), C(8)};
+    C a[19];
+    a[0] = drho / n2[0];
+    a[3] = (jx + Fx) / n2[3];
+    a[5] = (jy + Fy) / n2[5];
+    a[7] = (jz + Fz) / n2[7];
+#pragma unroll
+    for (int k = 1; k < 19; k++) {
+        if (k == 3 || k == 5 || k == 7) continue;
+        const C sk = C(p.s[k]);
+        a[k] = (m[k] - sk * (m[k] - meq[k]) + (C(1) - C(0.5) * sk) * mf[k]) * (C(1) / n2[k]);
+    }
+    // inverse transform M^T a, even/odd parts per opposite pair
+    o[0] = a[0] - C(30) * a[1] + C(12) * a[2];
+    const C Eax = a[0] - C(11) * a[1] - C(4) * a[2];
+    const C Edg = a[0] + C(8) * a[1] + a[2];
+    C E, O;
+    E = Eax + C(2) * a[9] - C(4) * a[10];
+    O = a[3] - C(4) * a[4];
+    o[1] = E + O; o[2] = E - O;
+    E = Eax - a[9] + C(2) * a[10] + a[11] - C(2) * a[12];
+    O = a[5] - C(4) * a[6];
+    o[3] = E + O; o[4] = E - O;
+    E = Eax - a[9] + C(2) * a[10] - a[11] + C(2) * a[12];
+    O = a[7] - C(4) * a[8];
+    o[5] = E + O; o[6] = E - O;
+    const C Exy = Edg + a[9] + a[10] + a[11] + a[12];
+    const C Exz = Edg + a[9] + a[10] - a[11] - a[12];
+    const C Eyz = Edg - C(2) * a[9] - C(2) * a[10];
+    const C ox = a[3] + a[4], oy = a[5] + a[6], oz = a[7] + a[8];
+    E = Exy + a[13]; O = ox + oy + a[16] - a[17];
+    o[7] = E + O; o[8] = E - O;
+    E = Exy - a[13]; O = ox - oy + a[16] + a[17];
+    o[9] = E + O; o[10] = E - O;
+    E = Exz + a[15]; O = ox + oz - a[16] + a[18];
+    o[11] = E + O; o[12] = E - O;
+    E = Exz - a[15]; O = ox - oz - a[16] - a[18];
+    o[13] = E + O; o[14] = E - O;
+    E = Eyz + a[14]; O = oy + oz + a[17] - a[18];
+    o[15] = E + O; o[16] = E - O;
+    E = Eyz - a[14]; O = oy - oz + a[17] + a[18];
+    o[17] = E + O; o[18] = E - O;
+}
+
+// D2Q9 basis rows: 1, 3q-4, (9q^2-21q+8)/2, ex, (3q-5)ex, ey, (3q-5)ey, ex^2-ey^2, exey;
+// squared norms 9, 36, 36, 6, 12, 6, 12, 4, 4.
+template <class C>
+__device__ __forceinline__ void collide_mrt_d2q9(const C *h, C *o, const StepParams &p) {
+    const C s1 = h[1] + h[2], d1 = h[1] - h[2];
+    const C s3 = h[3] + h[4], d3 = h[3] - h[4];
+    const C s5 = h[5] + h[6], d5 = h[5] - h[6];
+    const C s7 = h[7] + h[8], d7 = h[7] - h[8];
+    const C Sa = s1 + s3, Sd = s5 + s7;
+    const C drho = h[0] + Sa + Sd;
+    const C jx = d1 + d5 - d7;
+    const C jy = d3 + d5 + d7;
+    C m[9];
+    m[1] = C(-4) * h[0] - Sa + C(2) * Sd;
+    m[2] = C(4) * h[0] - C(2) * Sa + Sd;
+    m[4] = C(-2) * d1 + d5 - d7;
+    m[6] = C(-2) * d3 + d5 + d7;
+    m[7] = s1 - s3;
+    m[8] = s5 - s7;
+    const C rho = C(1) + drho;
+    const C irho = C(1) / rho;
+    C vx = jx * irho, vy = jy * irho, Fx = C(0), Fy = C(0);
+    if (p.has_force) {
+        vx += C(0.5) * C(p.g[0]);
+        vy += C(0.5) * C(p.g[1]);
+        Fx = rho * C(p.g[0]);
+        Fy = rho * C(p.g[1]);
+    }
+    const C vsq = vx * vx + vy * vy, vF = vx * Fx + vy * Fy;
+    C meq[9], mf[9];
+    meq[1] = C(-2) * drho + C(3) * rho * vsq;
+    meq[2] = drho - C(3) * rho * vsq;
+    meq[4] = -rho * vx;
+    meq[6] = -rho * vy;
+    meq[7] = rho * (vx * vx - vy * vy);
+    meq[8] = rho * vx * vy;
+    mf[1] = C(6) * vF;
+    mf[2] = C(-6) * vF;
+    mf[4] = -Fx;
+    mf[6] = -Fy;
+    mf[7] = C(2) * (vx * Fx - vy * Fy);
+    mf[8] = vx * Fy + vy * Fx;
+    const C n2[9] = {C(9), C(36), C(36), C(6), C(12), C(6), C(12), C(4), C(4)};
+    C a[9];
+    a[0] = drho / n2[0];
+    a[3] = (jx + Fx) / n2[3];
+    a[5] = (jy + Fy) / n2[5];
+#pragma unroll
+    for (int k = 1; k < 9; k++) {
+        if (k == 3 || k == 5) continue;
+        const C sk = C(p.s[k]);
+        a[k] = (m[k] - sk * (m[k] - meq[k]) + (C(1) - C(0.5) * sk) * mf[k]) * (C(1) / n2[k]);
+    }
+    o[0] = a[0] - C(4) * a[1] + C(4) * a[2];
+    const C Eax = a[0] - a[1] - C(2) * a[2], Edg = a[0] + C(2) * a[1] + a[2];
+    C E, O;
+    E = Eax + a[7]; O = a[3] - C(2) * a[4];
+    o[1] = E + O; o[2] = E - O;
+    E = Eax - a[7]; O = a[5] - C(2) * a[6];
+    o[3] = E + O; o[4] = E - O;
+    E = Edg + a[8]; O = a[3] + a[4] + a[5] + a[6];
+    o[5] = E + O; o[6] = E - O;
+    E = Edg - a[8]; O = -a[3] - a[4] + a[5] + a[6];
+    o[7] = E + O; o[8] = E - O;
+}
+
+template <class L, class C>
+__device__ __forceinline__ void collide_mrt(const C *h, C *o, const StepParams &p) {
+    if constexpr (L::Q == 19) collide_mrt_d3q19<C>(h, o, p);
+    else collide_mrt_d2q9<C>(h, o, p);
+}
+
+// ---------------------------------------------------------------------------- ELBM
+// Discrete entropic equilibrium p_i = w_i exp(b.e_i)/Z: the minimiser of
+// H = sum f ln(f/w) at fixed rho and rho u.  exp(b.e_i) is a product of per-axis
+// factors, so the state is kept as E+_a = expm1(b_a), E-_a = expm1(-b_a).  Start:
+// the product-form base (2u + sqrt(1+3u^2))/(1-u) per axis (entropic LBM subsection,
+// with the factor 3 under the root); then two Newton steps on the momentum constraint,
+// Jacobian = covariance of e under p.  Output heq_i = rho p_i - w_i (shifted space),
+// formed from expm1 values so the small deviation keeps its relative accuracy.
+template <class L, class C>
+__device__ __forceinline__ void entropic_heq(C drho, C rho, C ux, C uy, C uz, C *heq) {
+    C Ep[3], Em[3];
+    const C u[3] = {ux, uy, uz};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a >= L::D) {
+            Ep[a] = Em[a] = C(0);
+            continue;
+        }
+        const C s = sqrt(C(1) + C(3) * u[a] * u[a]);
+        const C t = C(3) * u[a] + C(3) * u[a] * u[a] / (s + C(1));  // 2u + s - (1 - u)
+        Ep[a] = t / (C(1) - u[a]);
+        Em[a] = -t / (C(2) * u[a] + s);
+    }
+    auto em1 = [&](int i) -> C {  // expm1(b . e_i)
+        C r = C(0);
+        int na = 0;
+        C fac[3];
+        const int e[3] = {L::ex(i), L::ey(i), L::ez(i)};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (e[a] == 1) fac[na++] = Ep[a];
+            if (e[a] == -1) fac[na++] = Em[a];
+        }
+        if (na == 1) r = fac[0];
+        if (na == 2) r = fac[0] + fac[1] + fac[0] * fac[1];
+        return r;
+    };
+    C dp[L::Q];  // p_i - w_i
+    for (int it = 0; it <= 2; it++) {
+        C zm1 = C(0);
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) zm1 += C(L::w(i)) * em1(i);
+        const C iz = C(1) / (C(1) + zm1);
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) dp[i] = C(L::w(i)) * (em1(i) - zm1) * iz;
+        if (it == 2) break;
+        // mean and covariance of e under p
+        C m[3] = {C(0), C(0), C(0)}, Cv[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) Cv[a][b] = (a == b && a < L::D) ? C(1.0 / 3.0) : C(0);
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) {
+            const int e[3] = {L::ex(i), L::ey(i), L::ez(i)};
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                if (e[a]) m[a] += C(e[a]) * dp[i];
+#pragma unroll
+                for (int b = 0; b < 3; b++)
+                    if (e[a] * e[b]) Cv[a][b] += C(e[a] * e[b]) * dp[i];
+            }
+        }
+        C r[3], d[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            r[a] = m[a] - u[a];
+#pragma unroll
+            for (int b = 0; b < 3; b++) Cv[a][b] -= m[a] * m[b];
+        }
+        if constexpr (L::D == 2) {
+            const C det = Cv[0][0] * Cv[1][1] - Cv[0][1] * Cv[1][0];
+            d[0] = (r[0] * Cv[1][1] - Cv[0][1] * r[1]) / det;
+            d[1] = (Cv[0][0] * r[1] - r[0] * Cv[1][0]) / det;
+            d[2] = C(0);
+        } else {
+            // inverse of the symmetric 3x3 covariance by cofactors
+            const C c00 = Cv[1][1] * Cv[2][2] - Cv[1][2] * Cv[2][1];
+            const C c01 = Cv[1][2] * Cv[2][0] - Cv[1][0] * Cv[2][2];
+            const C c02 = Cv[1][0] * Cv[2][1] - Cv[1][1] * Cv[2][0];
+            const C c11 = Cv[0][0] * Cv[2][2] - Cv[0][2] * Cv[2][0];
+            const C c12 = Cv[0][1] * Cv[2][0] - Cv[0][0] * Cv[2][1];
+            const C c22 = Cv[0][0] * Cv[1][1] - Cv[0][1] * Cv[1][0];
+            const C idet = C(1) / (Cv[0][0] * c00 + Cv[0][1] * c01 + Cv[0][2] * c02);
+            d[0] = (c00 * r[0] + c01 * r[1] + c02 * r[2]) * idet;
+            d[1] = (c01 * r[0] + c11 * r[1] + c12 * r[2]) * idet;
+            d[2] = (c02 * r[0] + c12 * r[1] + c22 * r[2]) * idet;
+        }
+        // b_a -= d_a  =>  E+ = E+ + (1+E+) expm1(-d), E- = E- + (1+E-) expm1(d)
+#pragma unroll
+        for (int a = 0; a < L::D; a++) {
+            const C em = expm1(-d[a]), ep = expm1(d[a]);
+            Ep[a] = Ep[a] + (C(1) + Ep[a]) * em;
+            Em[a] = Em[a] + (C(1) + Em[a]) * ep;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) heq[i] = rho * dp[i] + drho * C(L::w(i));
+}
+
+}  // namespace lbm

@@ -1,0 +1,137 @@
+// Entropic LBM: FP64 root of the entropy condition and the alpha MLP proposal.
+//
+// alpha is the nontrivial root of g(a) = H(f + a D) - H(f), D = feq - f, H = sum f ln(f/w)
+// (entropic LBM subsection, alpha condition).  Because feq is the exact constrained
+// minimiser and D carries no mass or momentum, sum_i D_i ln(feq_i/w_i) = 0 and
+//   g(a)  = sum_i f_i [ (1 + a d_i) log1p(a d_i) - a d_i log1p(d_i) ],   d_i = D_i/f_i
+//   g'(a) = sum_i f_i d_i [ log1p(a d_i) - log1p(d_i) ]
+// with no cancellation between two large H values.  g is convex, g(0) = 0, g'(0) < 0
+// and g(1) = H(feq) - H(f) <= 0, so the root lies in (1, a_max), a_max the largest
+// step keeping every population positive.  The paper notes alpha = 2 close to
+// equilibrium: nodes with max |d_i| < 1e-6 take alpha = 2 directly.  Otherwise
+// Newton with bisection safeguard on the bracket [lo, hi]; all in FP64 with
+// denormals kept (the paper reports flush-to-zero breaking ELBM).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lattice.hpp"
+#include "params.hpp"
+
+namespace lbm {
+
+struct AlphaOut {
+    double alpha;
+    int iters;
+    int converged;
+};
+
+constexpr double ALPHA_SHORTCUT = 1e-6;
+
+template <int Q>
+__device__ __forceinline__ AlphaOut alpha_newton(const double *f, const double *d, double a0, double amax,
+                                                 double tol, int maxit) {
+    double l1[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) l1[i] = log1p(d[i]);
+    double lo = 1.0, hi = amax, a = a0;
+    if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
+    for (int k = 1; k <= maxit; k++) {
+        double g = 0.0, dg = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const double ad = a * d[i];
+            const double la = log1p(ad);
+            g += f[i] * ((1.0 + ad) * la - ad * l1[i]);
+            dg += f[i] * d[i] * (la - l1[i]);
+        }
+        if (g == 0.0) return {a, k, 1};
+        if (g < 0.0) lo = a; else hi = a;
+        double an = a - g / dg;
+        if (fabs(an - a) <= tol) return {an, k, 1};
+        if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
+        a = an;
+    }
+    return {fmin(2.0, 0.99 * amax), maxit, 0};
+}
+
+// 6 -> 32 -> 32 -> 1 MLP, tanh hidden units, output 2 + linear; weights in LDS as
+// FP32 (converted from the BF16 copy), FP32 accumulation.  Layout: W1[32][6], b1[32],
+// W2[32][32], b2[32], w3[32], b3.
+__device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const float *x) {
+    const float *W1 = W, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    const float *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
+    float h1[MLP_H];
+#pragma unroll
+    for (int j = 0; j < MLP_H; j++) {
+        float s = b1[j];
+#pragma unroll
+        for (int k = 0; k < MLP_IN; k++) s = fmaf(W1[j * MLP_IN + k], x[k], s);
+        h1[j] = tanhf(s);
+    }
+    float y = 2.0f + b3[0];
+#pragma unroll 4
+    for (int j = 0; j < MLP_H; j++) {
+        float s = b2[j];
+#pragma unroll
+        for (int k = 0; k < MLP_H; k++) s = fmaf(W2[j * MLP_H + k], h1[k], s);
+        y = fmaf(w3[j], tanhf(s), y);
+    }
+    return y;
+}
+
+// The six alpha features: log10(a2/rho), a3/a2, a4/a2, max(-d), max(d), |v|^2/c_s^2,
+// with a_k = sum_i f_i d_i^k.
+template <int Q>
+__device__ __forceinline__ void alpha_features(const double *f, const double *d, double rho, double vsq,
+                                               float *x) {
+    double a2 = 0.0, a3 = 0.0, a4 = 0.0, mneg = -1e300, mpos = -1e300;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const double fd2 = f[i] * d[i] * d[i];
+        a2 += fd2;
+        a3 += fd2 * d[i];
+        a4 += fd2 * d[i] * d[i];
+        mneg = fmax(mneg, -d[i]);
+        mpos = fmax(mpos, d[i]);
+    }
+    x[0] = float(log10(a2 / rho));
+    x[1] = float(a3 / a2);
+    x[2] = float(a4 / a2);
+    x[3] = float(mneg);
+    x[4] = float(mpos);
+    x[5] = float(3.0 * vsq);
+}
+
+// Full alpha for one node.  f[i] = populations, D[i] = feq_i - f_i (FP64).
+template <int Q>
+__device__ __forceinline__ AlphaOut alpha_solve(const double *f, const double *D, double rho, double vsq,
+                                                const StepParams &p, const float *mlp_lds) {
+    double d[Q], dmax = 0.0, amax = INFINITY;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        d[i] = D[i] / f[i];
+        dmax = fmax(dmax, fabs(d[i]));
+        if (d[i] < 0.0) amax = fmin(amax, -1.0 / d[i]);
+    }
+    if (dmax < ALPHA_SHORTCUT) return {2.0, 0, 1};
+    double a0 = 2.0;
+    if (p.alpha_init == 1) {
+        double a2 = 0.0, a3 = 0.0, a4 = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const double fd2 = f[i] * d[i] * d[i];
+            a2 += fd2;
+            a3 += fd2 * d[i];
+            a4 += fd2 * d[i] * d[i];
+        }
+        a0 = 2.0 + (a3 - 2.0 * a4) / (3.0 * a2);
+    } else if (p.alpha_init == 2 && mlp_lds) {
+        float x[MLP_IN];
+        alpha_features<Q>(f, d, rho, vsq, x);
+        a0 = double(mlp_eval_lds(mlp_lds, x));
+    }
+    return alpha_newton<Q>(f, d, a0, amax, p.alpha_tol, p.alpha_maxit);
+}
+
+}  // namespace lbm

@@ -1,0 +1,303 @@
+// The ELBM alpha proposal MLP: training data sampler, inference and training kernels.
+//
+// The network (6 -> 32 -> 32 -> 1, tanh hidden units, output 2 + linear) proposes the
+// first Newton iterate of the entropic alpha; Newton remains the judge of the result.
+// Training is plain minibatch MSE with Adam in FP32; gradients are reduced across a
+// wave with lane shuffles, then across the waves of a block and across blocks in a
+// fixed order, so a training run is deterministic.
+#include "dispatch.hpp"
+#include "step.hpp"
+
+namespace lbm {
+
+namespace {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {  // SplitMix64 finaliser
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+template <class L, class St>
+__global__ __launch_bounds__(256) void k_alpha_dataset(MlpDatasetParams d) {
+    using T = typename St::T;
+    using C = typename St::C;
+    constexpr int Q = L::Q;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= d.n) return;
+    const StepParams &p = d.sp;
+    const uint32_t n = uint32_t(mix64(d.seed ^ uint64_t(k)) % uint64_t(p.N));
+    const int x = int(n % uint32_t(p.nx)), y = int((n / uint32_t(p.nx)) % uint32_t(p.ny));
+    const int z = int(n / (uint32_t(p.nx) * uint32_t(p.ny)));
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
+    float *feat = d.feat + 6 * k;
+    if (p.flags && p.flags[n] == 1) {
+        for (int j = 0; j < 6; j++) feat[j] = 0.0f;
+        d.alpha[k] = 2.0;
+        d.valid[k] = 0;
+        return;
+    }
+    const T *src = static_cast<const T *>(p.src);
+    C h[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        int slot;
+        uint32_t nd;
+        canon_loc<L>(d.layout, i, g, slot, nd);
+        h[i] = St::decode(src[size_t(slot) * p.N + nd], C(L::w(i)));
+    }
+    const Macro<C> m = moments<L, C>(h);
+    const C irho = C(1) / m.rho;
+    const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
+    C heq[Q];
+    entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
+    double f[Q], dd[Q], dmax = 0.0, amax = INFINITY;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        f[i] = L::w(i) + double(h[i]);
+        dd[i] = (double(heq[i]) - double(h[i])) / f[i];
+        dmax = fmax(dmax, fabs(dd[i]));
+        if (dd[i] < 0.0) amax = fmin(amax, -1.0 / dd[i]);
+    }
+    const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
+    float xf[MLP_IN];
+    if (dmax < ALPHA_SHORTCUT) {
+        for (int j = 0; j < 6; j++) feat[j] = 0.0f;
+        d.alpha[k] = 2.0;
+        d.valid[k] = 0;
+        return;
+    }
+    alpha_features<Q>(f, dd, double(m.rho), vsq, xf);
+    const AlphaOut ao = alpha_newton<Q>(f, dd, 2.0, amax, p.alpha_tol, p.alpha_maxit);
+    for (int j = 0; j < 6; j++) feat[j] = xf[j];
+    d.alpha[k] = ao.alpha;
+    d.valid[k] = ao.converged ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward_bf16(const uint16_t *wb, const float *x, int64_t n, float *y) {
+    __shared__ float s_w[MLP_NPARAM];
+    for (int k = threadIdx.x; k < MLP_NPARAM; k += blockDim.x) s_w[k] = __uint_as_float(uint32_t(wb[k]) << 16);
+    __syncthreads();
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    float xr[MLP_IN];
+    for (int j = 0; j < MLP_IN; j++) xr[j] = x[MLP_IN * r + j];
+    y[r] = mlp_eval_lds(s_w, xr);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+constexpr int TB = MLP_TRAIN_BLOCK;  // threads per training block
+constexpr int TW = TB / 64;        // waves per block
+
+// One block = up to TB samples.  Sample r of the batch is row idx(r) of the data,
+// idx(r) = (a r + b) mod n_all when a permutation is given (a coprime to n_all), the
+// identity otherwise.  Inputs are normalised as (x - mu) * isd.  Writes the block's
+// gradient (sum over its samples of d loss / d w, loss = mean over the batch) and
+// squared-error sum into partials[block][MLP_NPARAM + 1].
+__global__ __launch_bounds__(TB) void k_mlp_grad(const float *w, const float *xall, const double *tall,
+                                                 int64_t row0, int64_t nbatch, int64_t n_all, uint64_t pa,
+                                                 uint64_t pb, const float *mu, const float *isd,
+                                                 float *partials) {
+    __shared__ float s_w[MLP_NPARAM];
+    __shared__ float s_g[TW][MLP_NPARAM + 1];
+    for (int k = threadIdx.x; k < MLP_NPARAM; k += TB) s_w[k] = w[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r = int64_t(blockIdx.x) * TB + threadIdx.x;
+    const bool live = r < nbatch;
+    float x[MLP_IN] = {0, 0, 0, 0, 0, 0};
+    float t = 2.0f;
+    if (live) {
+        const int64_t gr = row0 + r;
+        const int64_t row = pa ? int64_t((pa * uint64_t(gr) + pb) % uint64_t(n_all)) : gr;
+        for (int j = 0; j < MLP_IN; j++) x[j] = (xall[MLP_IN * row + j] - mu[j]) * isd[j];
+        t = float(tall[row]);
+    }
+    const float *W1 = s_w, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    const float *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
+    float h1[MLP_H], h2[MLP_H];
+#pragma unroll
+    for (int j = 0; j < MLP_H; j++) {
+        float s = b1[j];
+#pragma unroll
+        for (int k = 0; k < MLP_IN; k++) s = fmaf(W1[j * MLP_IN + k], x[k], s);
+        h1[j] = tanhf(s);
+    }
+    float yv = 2.0f + b3[0];
+#pragma unroll 4
+    for (int j = 0; j < MLP_H; j++) {
+        float s = b2[j];
+#pragma unroll
+        for (int k = 0; k < MLP_H; k++) s = fmaf(W2[j * MLP_H + k], h1[k], s);
+        h2[j] = tanhf(s);
+        yv = fmaf(w3[j], h2[j], yv);
+    }
+    const float err = live ? (yv - t) : 0.0f;
+    const float dy = live ? 2.0f * err / float(nbatch) : 0.0f;
+    float *gW1 = s_g[wv], *gb1 = gW1 + MLP_H * MLP_IN, *gW2 = gb1 + MLP_H, *gb2 = gW2 + MLP_H * MLP_H;
+    float *gw3 = gb2 + MLP_H, *gb3 = gw3 + MLP_H;
+    {
+        const float v = wave_sum(dy);
+        if (lane == 0) gb3[0] = v;
+        const float e2 = wave_sum(err * err);
+        if (lane == 0) s_g[wv][MLP_NPARAM] = e2;
+    }
+    float d2[MLP_H];
+#pragma unroll
+    for (int j = 0; j < MLP_H; j++) {
+        const float v = wave_sum(dy * h2[j]);
+        if (lane == 0) gw3[j] = v;
+        d2[j] = dy * w3[j] * (1.0f - h2[j] * h2[j]);
+    }
+#pragma unroll 2
+    for (int j = 0; j < MLP_H; j++) {
+        const float vb = wave_sum(d2[j]);
+        if (lane == 0) gb2[j] = vb;
+#pragma unroll
+        for (int k = 0; k < MLP_H; k++) {
+            const float v = wave_sum(d2[j] * h1[k]);
+            if (lane == 0) gW2[j * MLP_H + k] = v;
+        }
+    }
+#pragma unroll 2
+    for (int k = 0; k < MLP_H; k++) {
+        float s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < MLP_H; j++) s = fmaf(W2[j * MLP_H + k], d2[j], s);
+        const float d1 = s * (1.0f - h1[k] * h1[k]);
+        const float vb = wave_sum(d1);
+        if (lane == 0) gb1[k] = vb;
+#pragma unroll
+        for (int m = 0; m < MLP_IN; m++) {
+            const float v = wave_sum(d1 * x[m]);
+            if (lane == 0) gW1[k * MLP_IN + m] = v;
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += TB) {
+        float acc = 0.0f;
+        for (int q = 0; q < TW; q++) acc += s_g[q][k];
+        partials[size_t(blockIdx.x) * (MLP_NPARAM + 1) + k] = acc;
+    }
+}
+
+__global__ void k_mlp_reduce(const float *partials, int nparts, float *grad, double *loss_acc, int64_t nbatch) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > MLP_NPARAM) return;
+    double acc = 0.0;
+    for (int b = 0; b < nparts; b++) acc += double(partials[size_t(b) * (MLP_NPARAM + 1) + k]);
+    if (k < MLP_NPARAM) grad[k] = float(acc);
+    else if (loss_acc) *loss_acc += acc / double(nbatch);
+}
+
+__global__ void k_adam(float *w, const float *g, float *m, float *v, float b1t, float b2t, float lr) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= MLP_NPARAM) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float mk = b1 * m[k] + (1.0f - b1) * g[k];
+    const float vk = b2 * v[k] + (1.0f - b2) * g[k] * g[k];
+    m[k] = mk;
+    v[k] = vk;
+    const float mh = mk / (1.0f - b1t), vh = vk / (1.0f - b2t);
+    w[k] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_to_bf16(const float *w, uint16_t *wb) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= MLP_NPARAM) return;
+    wb[k] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(w[k]));
+}
+
+// sums and sums of squares of the 6 features (FP64, fixed-order two-level reduction)
+__global__ __launch_bounds__(256) void k_moments(const float *x, int64_t n, double *partials) {
+    __shared__ double s[12][256];
+    double acc[12] = {0};
+    for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n; r += int64_t(gridDim.x) * 256)
+        for (int j = 0; j < 6; j++) {
+            const double v = x[6 * r + j];
+            acc[j] += v;
+            acc[6 + j] += v * v;
+        }
+    for (int j = 0; j < 12; j++) s[j][threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int j = 0; j < 12; j++) s[j][threadIdx.x] += s[j][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 12) partials[blockIdx.x * 12 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_moments_final(const double *partials, int nb, double *out) {
+    const int j = threadIdx.x;
+    if (j >= 12) return;
+    double a = 0.0;
+    for (int b = 0; b < nb; b++) a += partials[b * 12 + j];
+    out[j] = a;
+}
+
+}  // namespace
+
+hipError_t launch_alpha_dataset(int lattice, int storage, const MlpDatasetParams &p, hipStream_t s) {
+    return with_lattice(lattice, [&](auto lt) {
+        using L = decltype(lt);
+        return with_storage<false>(storage, 0, [&](auto st) {
+            using St = decltype(st);
+            const int64_t nb = (p.n + 255) / 256;
+            k_alpha_dataset<L, St><<<dim3(uint32_t(nb)), 256, 0, s>>>(p);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t mlp_forward_bf16(const uint16_t *w, const float *x, int64_t n, float *y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_mlp_forward_bf16<<<dim3(uint32_t((n + 255) / 256)), 256, 0, s>>>(w, x, n, y);
+    return hipGetLastError();
+}
+
+// grad of the mean loss over rows [0, n) of (x, t) in order (no permutation).
+hipError_t mlp_loss_grad(const float *w, const float *x, const double *t, int64_t n, const float *mu,
+                         const float *isd, float *partials, int nparts, float *grad, double *loss, hipStream_t s) {
+    if (n <= 0 || nparts < int((n + TB - 1) / TB)) return hipErrorInvalidValue;
+    const int nb = int((n + TB - 1) / TB);
+    k_mlp_grad<<<nb, TB, 0, s>>>(w, x, t, 0, n, n, 0, 0, mu, isd, partials);
+    k_mlp_reduce<<<(MLP_NPARAM + 1 + 255) / 256, 256, 0, s>>>(partials, nb, grad, loss, n);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(float *w, const float *grad, float *m, float *v, int t, float lr, hipStream_t s) {
+    const float b1t = powf(0.9f, float(t)), b2t = powf(0.999f, float(t));
+    k_adam<<<(MLP_NPARAM + 255) / 256, 256, 0, s>>>(w, grad, m, v, b1t, b2t, lr);
+    return hipGetLastError();
+}
+
+hipError_t mlp_to_bf16(const float *w, uint16_t *wb, hipStream_t s) {
+    k_to_bf16<<<(MLP_NPARAM + 255) / 256, 256, 0, s>>>(w, wb);
+    return hipGetLastError();
+}
+
+hipError_t mlp_moments(const float *x, int64_t n, double *acc, hipStream_t s) {
+    const int nb = 64;
+    k_moments<<<nb, 256, 0, s>>>(x, n, acc + 12);
+    k_moments_final<<<1, 64, 0, s>>>(acc + 12, nb, acc);
+    return hipGetLastError();
+}
+
+// One training minibatch: rows row0 .. row0 + nbatch - 1 of the permuted order.
+hipError_t mlp_train_batch(const float *w, const float *x, const double *t, int64_t row0, int64_t nbatch,
+                           int64_t n_all, uint64_t pa, uint64_t pb, const float *mu, const float *isd,
+                           float *partials, float *grad, double *loss_acc, hipStream_t s) {
+    const int nb = int((nbatch + TB - 1) / TB);
+    k_mlp_grad<<<nb, TB, 0, s>>>(w, x, t, row0, nbatch, n_all, pa, pb, mu, isd, partials);
+    k_mlp_reduce<<<(MLP_NPARAM + 1 + 255) / 256, 256, 0, s>>>(partials, nb, grad, loss_acc, nbatch);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

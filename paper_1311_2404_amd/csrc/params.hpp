@@ -1,0 +1,43 @@
+// Kernel parameter block shared by the launchers and the kernels.
+#pragma once
+#include <stdint.h>
+
+namespace lbm {
+
+enum Layout { LAYOUT_AB = 0, LAYOUT_AA_EVEN = 1, LAYOUT_AA_ODD = 2 };
+enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3 };
+
+constexpr int MLP_IN = 6;
+constexpr int MLP_H = 32;
+constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 1313
+constexpr int NEWTON_BINS = 32;
+
+// Passed by value as the kernel argument of every step-like kernel.
+struct StepParams {
+    int nx, ny, nz;
+    uint32_t N;                 // nodes per component
+    const void *src;            // populations read (AB: current copy; AA: the single copy)
+    void *dst;                  // populations written (AB: the other copy; AA: == src)
+    const uint8_t *flags;       // node flags or nullptr
+    // physics
+    double omega;               // 1/tau
+    double g[3];                // body acceleration
+    int has_force;
+    double s[19];               // MRT rates in moment order
+    // entropic LBM
+    double beta;                // 1/(2 tau)
+    double alpha_tol;
+    int alpha_maxit;
+    int alpha_init;             // 0: 2, 1: series, 2: MLP
+    const uint16_t *mlp;        // bf16 MLP weights (alpha_init == 2)
+    unsigned long long *stats;  // [NEWTON_BINS] histogram + [1] non-converged, or nullptr
+    // Shan-Chen
+    const void *psi;            // psi[2][N] in compute precision
+    double G;
+    int psi_mode;               // 0: psi = rho, 1: 1 - exp(-rho)
+    // stochastic rounding stream
+    uint32_t seed;
+    uint32_t step;
+};
+
+}  // namespace lbm

@@ -1,0 +1,298 @@
+// The fused stream-and-collide kernel (one thread per node) and its two-component
+// Shan-Chen variant.
+//
+// Streaming patterns (GPU-algorithms subsection of the paper, AB and AA):
+//   AB      : read the population arriving along e_i from node x - e_i of copy A
+//             (propagate on read), write the post-collision value to node x of copy B.
+//             Copy A therefore holds post-collision values; the physical population
+//             f_i(x, t) is A[i][x - e_i].
+//   AA even : read slot i of node x, write the post-collision f*_i to slot opp(i) of x.
+//   AA odd  : read slot opp(i) of node x - e_i, write f*_i to slot i of node x + e_i.
+//             Each thread reads and writes exactly the same locations, so the single
+//             copy is updated in place without races; after an odd step the layout is
+//             the plain one again.
+// Rows along x are contiguous (SoA f[q][z][y][x]); a workgroup covers whole x rows when
+// nx allows, so the +-1 shifted reads along x stay inside cache lines the same
+// workgroup also reads.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "collide.hpp"
+#include "elbm.hpp"
+#include "lattice.hpp"
+#include "params.hpp"
+#include "storage.hpp"
+
+namespace lbm {
+
+struct Geo {
+    int x, y, z, xm, xp, ym, yp, zm, zp;
+    uint32_t nx, ny;
+    __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const {
+        const int xx = dx == 0 ? x : (dx > 0 ? xp : xm);
+        const int yy = dy == 0 ? y : (dy > 0 ? yp : ym);
+        const int zz = dz == 0 ? z : (dz > 0 ? zp : zm);
+        return (uint32_t(zz) * ny + uint32_t(yy)) * nx + uint32_t(xx);
+    }
+};
+
+__device__ __forceinline__ Geo make_geo(int x, int y, int z, int nx, int ny, int nz) {
+    Geo g;
+    g.x = x;
+    g.y = y;
+    g.z = z;
+    g.xm = (x == 0 ? nx : x) - 1;
+    g.xp = (x + 1 == nx) ? 0 : x + 1;
+    g.ym = (y == 0 ? ny : y) - 1;
+    g.yp = (y + 1 == ny) ? 0 : y + 1;
+    g.zm = (z == 0 ? nz : z) - 1;
+    g.zp = (z + 1 == nz) ? 0 : z + 1;
+    g.nx = uint32_t(nx);
+    g.ny = uint32_t(ny);
+    return g;
+}
+
+// Where the physical population f_i(x) currently lives (slot, node).
+template <class L>
+__device__ __forceinline__ void canon_loc(int layout, int i, const Geo &g, int &slot, uint32_t &node) {
+    if (layout == LAYOUT_AA_EVEN) {
+        slot = i;
+        node = g.at(0, 0, 0);
+    } else {
+        slot = layout == LAYOUT_AB ? i : opp(i);
+        node = g.at(-L::ex(i), -L::ey(i), -L::ez(i));
+    }
+}
+
+// Where the post-collision value f*_i of node x is written.
+template <class L>
+__device__ __forceinline__ void post_loc(int layout, int i, const Geo &g, int &slot, uint32_t &node) {
+    if (layout == LAYOUT_AB) {
+        slot = i;
+        node = g.at(0, 0, 0);
+    } else if (layout == LAYOUT_AA_EVEN) {
+        slot = opp(i);
+        node = g.at(0, 0, 0);
+    } else {
+        slot = i;
+        node = g.at(L::ex(i), L::ey(i), L::ez(i));
+    }
+}
+
+template <class St>
+__device__ __forceinline__ uint32_t sr_bits(const StepParams &p, uint32_t n, int i, uint32_t step_key) {
+    return hash32((n * 19u + uint32_t(i)) ^ step_key);
+}
+
+template <class L, class St, int MODEL, int LAYOUT, bool FLAGS>
+__global__ __launch_bounds__(512) void k_step(StepParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    constexpr int Q = L::Q;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nthr = blockDim.x * blockDim.y;
+
+    // ELBM only: MLP weights (FP32 from BF16) and the Newton-iteration histogram in LDS
+    __shared__ float s_mlp[MODEL == M_ELBM ? MLP_NPARAM : 1];
+    __shared__ uint32_t s_hist[MODEL == M_ELBM ? NEWTON_BINS + 1 : 1];
+    if constexpr (MODEL == M_ELBM) {
+        if (p.alpha_init == 2 && p.mlp) {
+            for (int k = tid; k < MLP_NPARAM; k += nthr) s_mlp[k] = __uint_as_float(uint32_t(p.mlp[k]) << 16);
+        }
+        if (p.stats)
+            for (int k = tid; k < NEWTON_BINS + 1; k += nthr) s_hist[k] = 0u;
+        if ((p.alpha_init == 2 && p.mlp) || p.stats) __syncthreads();
+    }
+
+    const bool active = x < p.nx && y < p.ny;
+    if (active) {
+        const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
+        const uint32_t n = g.at(0, 0, 0);
+        const uint32_t N = p.N;
+        // no __restrict__: with AA the two pointers are the same copy
+        const T *src = static_cast<const T *>(p.src);
+        T *dst = static_cast<T *>(p.dst);
+        T raw[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            int slot;
+            uint32_t nd;
+            canon_loc<L>(LAYOUT, i, g, slot, nd);
+            raw[i] = src[size_t(slot) * N + nd];
+        }
+        T out[Q];
+        const bool wall = FLAGS && p.flags[n] == 1;
+        if (wall) {
+            // full-way bounce-back: the stored values are returned along -e_i untouched
+#pragma unroll
+            for (int i = 0; i < Q; i++) out[i] = raw[opp(i)];
+        } else {
+            C h[Q], o[Q];
+#pragma unroll
+            for (int i = 0; i < Q; i++) h[i] = St::decode(raw[i], C(L::w(i)));
+            if constexpr (MODEL == M_BGK) {
+                collide_bgk<L, C>(h, o, p);
+            } else if constexpr (MODEL == M_MRT) {
+                collide_mrt<L, C>(h, o, p);
+            } else {
+                const Macro<C> m = moments<L, C>(h);
+                const C irho = C(1) / m.rho;
+                const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
+                C heq[Q];
+                entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
+                double f[Q], D[Q];
+#pragma unroll
+                for (int i = 0; i < Q; i++) {
+                    f[i] = L::w(i) + double(h[i]);
+                    D[i] = double(heq[i]) - double(h[i]);
+                }
+                const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
+                const AlphaOut ao = alpha_solve<Q>(f, D, double(m.rho), vsq, p,
+                                                   (p.alpha_init == 2 && p.mlp) ? s_mlp : nullptr);
+                const C ab = C(ao.alpha * p.beta);
+#pragma unroll
+                for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
+                if (p.stats) {
+                    atomicAdd(&s_hist[ao.iters < NEWTON_BINS ? ao.iters : NEWTON_BINS - 1], 1u);
+                    if (!ao.converged) atomicAdd(&s_hist[NEWTON_BINS], 1u);
+                }
+            }
+            uint32_t key = 0;
+            if constexpr (sizeof(T) == 2) key = hash32(p.seed ^ hash32(p.step + 0x9e3779b9u));
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                uint32_t rnd = 0;
+                if constexpr (sizeof(T) == 2) rnd = sr_bits<St>(p, n, i, key);
+                out[i] = St::encode(o[i], C(L::w(i)), rnd);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            int slot;
+            uint32_t nd;
+            post_loc<L>(LAYOUT, i, g, slot, nd);
+            dst[size_t(slot) * N + nd] = out[i];
+        }
+    }
+    if constexpr (MODEL == M_ELBM) {
+        if (p.stats) {
+            __syncthreads();
+            for (int k = tid; k < NEWTON_BINS + 1; k += nthr)
+                if (s_hist[k]) atomicAdd(&p.stats[k], (unsigned long long)s_hist[k]);
+        }
+    }
+}
+
+// Shan-Chen pre-pass (the paper's macroscopic-field kernel): psi_c(x) of both components
+// from the populations that stream into x at this step.
+template <class L, class St, int LAYOUT>
+__global__ __launch_bounds__(512) void k_psi(StepParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
+    const uint32_t n = g.at(0, 0, 0);
+    const T *src = static_cast<const T *>(p.src);
+    C *psi = static_cast<C *>(const_cast<void *>(p.psi));
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        const T *fc = src + size_t(c) * L::Q * p.N;
+        C r = C(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            int slot;
+            uint32_t nd;
+            canon_loc<L>(LAYOUT, i, g, slot, nd);
+            r += St::decode(fc[size_t(slot) * p.N + nd], C(L::w(i)));
+        }
+        const C rho = C(1) + r;
+        psi[size_t(c) * p.N + n] = p.psi_mode == 1 ? C(1) - exp(-rho) : rho;
+    }
+}
+
+// Two-component Shan-Chen step: both components in one pass (they share the common
+// velocity), equal relaxation times, EDM forcing.
+template <class L, class St, int LAYOUT>
+__global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    constexpr int Q = L::Q;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
+    const uint32_t n = g.at(0, 0, 0);
+    const uint32_t N = p.N;
+    const T *src = static_cast<const T *>(p.src);
+    T *dst = static_cast<T *>(p.dst);
+    const C *__restrict__ psi = static_cast<const C *>(p.psi);
+
+    C h[2][Q];
+    Macro<C> m[2];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            int slot;
+            uint32_t nd;
+            canon_loc<L>(LAYOUT, i, g, slot, nd);
+            h[c][i] = St::decode(src[(size_t(c) * Q + slot) * N + nd], C(L::w(i)));
+        }
+        m[c] = moments<L, C>(h[c]);
+    }
+    // interaction forces: F_c = -G psi_c(x) sum_i w_i psi_other(x + e_i) e_i + rho_c g
+    C F[2][3];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        const C *po = psi + size_t(1 - c) * N;
+        C sx = C(0), sy = C(0), sz = C(0);
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            const C v = C(L::w(i)) * po[g.at(L::ex(i), L::ey(i), L::ez(i))];
+            sx += C(L::ex(i)) * v;
+            sy += C(L::ey(i)) * v;
+            sz += C(L::ez(i)) * v;
+        }
+        const C a = -C(p.G) * psi[size_t(c) * N + n];
+        F[c][0] = a * sx + m[c].rho * C(p.g[0]);
+        F[c][1] = a * sy + m[c].rho * C(p.g[1]);
+        F[c][2] = a * sz + m[c].rho * C(L::D == 3 ? p.g[2] : 0.0);
+    }
+    const C irs = C(1) / (m[0].rho + m[1].rho);
+    const C ux = (m[0].jx + m[1].jx) * irs, uy = (m[0].jy + m[1].jy) * irs, uz = (m[0].jz + m[1].jz) * irs;
+    const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
+    const C omega = C(p.omega);
+    const uint32_t key = sizeof(T) == 2 ? hash32(p.seed ^ hash32(p.step + 0x9e3779b9u)) : 0u;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        const C ir = C(1) / m[c].rho;
+        const C dx = F[c][0] * ir, dy = F[c][1] * ir, dz = F[c][2] * ir;
+        // feq(rho, u + du) - feq(rho, u) expanded so that it carries no cancellation
+        const C du15 = C(1.5) * (dx * (C(2) * ux + dx) + dy * (C(2) * uy + dy) + dz * (C(2) * uz + dz));
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            const C w = C(L::w(i));
+            const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
+            const C ed = C(L::ex(i)) * dx + C(L::ey(i)) * dy + C(L::ez(i)) * dz;
+            const C heq = w * (m[c].drho + m[c].rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
+            const C edm = w * m[c].rho * (C(3) * ed + C(4.5) * ed * (C(2) * eu + ed) - du15);
+            const C o = h[c][i] + omega * (heq - h[c][i]) + edm;
+            uint32_t rnd = 0;
+            if constexpr (sizeof(T) == 2) rnd = hash32(((n * 19u + uint32_t(i)) * 2u + uint32_t(c)) ^ key);
+            int slot;
+            uint32_t nd;
+            post_loc<L>(LAYOUT, i, g, slot, nd);
+            dst[(size_t(c) * Q + slot) * N + nd] = St::encode(o, w, rnd);
+        }
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,23 @@
+// Step-kernel instantiations for the LBGK collision (all storages, layouts, flag modes).
+#include "dispatch.hpp"
+#include "step.hpp"
+
+namespace lbm {
+
+hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+                           const LaunchCfg &c) {
+    return with_lattice(lattice, [&](auto lt) {
+        using L = decltype(lt);
+        return with_storage<true>(storage, sr, [&](auto st) {
+            using St = decltype(st);
+            return with_layout(layout, [&](auto lay) {
+                constexpr int LAY = decltype(lay)::value;
+                if (flags) k_step<L, St, M_BGK, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
+                else k_step<L, St, M_BGK, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                return hipGetLastError();
+            });
+        });
+    });
+}
+
+}  // namespace lbm

@@ -1,0 +1,104 @@
+"""The C ABI: every entry point declared in include/lbm.h is exported by the built
+library, and argument errors are reported without touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "lbm.h")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import paper_1311_2404_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("liblbm.so not built")
+    return P
+
+
+def test_header_and_binding_agree(lbm):
+    assert _declared() == sorted(lbm.ENTRY_POINTS)
+
+
+def test_library_exports_every_declared_symbol(lbm):
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (lbm_[a-z_0-9]+)$", out, flags=re.M))
+    missing = [s for s in _declared() if s not in exported]
+    assert not missing, missing
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    for s in _declared():
+        assert getattr(L, s) is not None
+
+
+@pytest.mark.parametrize("args,code", [
+    ((5, 0, 8, 8, 1, 0.8), -1),      # unknown lattice
+    ((0, 9, 8, 8, 1, 0.8), -1),      # unknown model
+    ((0, 0, 0, 8, 1, 0.8), -1),      # empty grid
+    ((0, 0, 8, 8, 2, 0.8), -1),      # D2Q9 with nz > 1
+    ((1, 0, 8, 8, 8, 0.5), -1),      # tau must exceed 1/2
+    ((1, 0, 8, 8, 8, float("nan")), -1),
+    ((1, 0, 70000, 70000, 1000, 0.8), -1),  # N >= 2^32
+])
+def test_create_rejects_bad_arguments(lbm, args, code):
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create(*args)
+    assert ei.value.code == code
+    assert lbm.lbm_last_error(None)
+
+
+def test_elbm_rejects_force_and_state_errors(lbm):
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_ELBM, 4, 4, 4, 0.6, (1e-5, 0, 0))
+    assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    h = lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_BGK, 4, 4, 4, 0.6)
+    try:
+        for call, code in [(lambda: lbm.lbm_step(h, 1), lbm.LBM_ESTATE),
+                           (lambda: lbm.lbm_step(h, -1), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_get_f(h, np.zeros((1, 19, 64))), lbm.LBM_ESTATE),
+                           (lambda: lbm.lbm_set_storage(h, 9), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_set_storage(h, lbm.LBM_F32, 0, 1), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_set_mrt_rates(h, np.ones(9)), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_set_mrt_rates(h, np.full(19, 2.5)), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_set_elbm(h, 3), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_set_elbm(h, 0, -1.0), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_set_shanchen(h, float("inf")), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_mlp_set_weights(h, np.zeros(10)), lbm.LBM_EINVAL),
+                           (lambda: lbm.lbm_mlp_get_weights(h), None)]:
+            if code is None:
+                call()
+                continue
+            with pytest.raises(lbm.LbmError) as ei:
+                call()
+            assert ei.value.code == code
+    finally:
+        lbm.lbm_destroy(h)
+    lbm.lbm_destroy(None)
+
+
+def test_shan_chen_rejects_walls_and_sr(lbm):
+    h = lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_SHANCHEN, 4, 4, 4, 1.0)
+    try:
+        fl = np.zeros(64, np.uint8)
+        fl[0] = 1
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_flags(h, fl)
+        assert ei.value.code == lbm.LBM_EUNSUPPORTED
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_storage(h, lbm.LBM_BF16S, lbm.LBM_AB, 1)
+        assert ei.value.code == lbm.LBM_EUNSUPPORTED
+        bad = np.full(64, 3, np.uint8)
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_flags(h, bad)
+        assert ei.value.code == lbm.LBM_EINVAL
+    finally:
+        lbm.lbm_destroy(h)
