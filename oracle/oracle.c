@@ -7,7 +7,11 @@
  *
  * Every step is written the plain way: gather a node's populations, collide
  * them (or swap them on a wall node), push each post-collision value to
- * x + e_i in a second array, swap arrays.  All arithmetic is double precision.
+ * x + e_i in a second array, swap arrays.  All arithmetic is double precision, on
+ * the deviations h_i = f_i - w_i (the paper's round-off minimising formulation, from
+ * its single-vs-double precision subsection): with f stored directly, double
+ * rounding of rho = sum f and of the O(w) offset drifts f - w by ~1e-16 per step,
+ * which over thousands of steps exceeds 1e-12 relative on slow flows.
  * Citations name the section / equation of Januszewski & Kostur, "Sailfish: a
  * flexible multi-GPU implementation of the lattice Boltzmann method" (CPC 2014).
  *
@@ -117,6 +121,19 @@ void orc_feq(int lattice, double rho, const double *u, double *feq) {
     feq_poly(&L, rho, u, feq);
 }
 
+/* The same equilibrium minus the rest weights, written with drho = rho - 1 (the
+ * round-off minimising formulation of the single-vs-double precision subsection, which
+ * keeps the small deviation f - w instead of f):
+ * feq_i - w_i = w_i (drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u^2)). */
+static void heq_poly(const lattice_t *L, double drho, const double *u, double *heq) {
+    double rho = 1.0 + drho;
+    double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < L->q; i++) {
+        double eu = L->e[i][0] * u[0] + L->e[i][1] * u[1] + L->e[i][2] * u[2];
+        heq[i] = L->w[i] * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+    }
+}
+
 /* Solve the d x d system A x = r (d = 2 or 3) by Cramer's rule. */
 static void solve_small(int d, double A[3][3], const double *r, double *x) {
     if (d == 2) {
@@ -143,8 +160,10 @@ static void solve_small(int d, double A[3][3], const double *r, double *x) {
  * rho and rho u (entropic LBM subsection).  Its form is rho w_i exp(b.e_i)/Z.
  * The first guess b_a = ln((2u_a + sqrt(1+3u_a^2))/(1-u_a)) is the product form's
  * exponent base; two Newton steps on the momentum constraint follow (Jacobian =
- * covariance of e under the normalised weights). */
-static void feq_entropic(const lattice_t *L, double rho, const double *u, double *feq) {
+ * covariance of e under the normalised weights).  Returned as dp_i = p_i - w_i with
+ * p_i = w_i exp(b.e_i)/Z, evaluated through expm1 so the small deviation keeps its
+ * relative accuracy: dp_i = w_i (expm1(b.e_i) - (Z - 1))/Z. */
+static void entropic_dp(const lattice_t *L, const double *u, double *dp) {
     double b[3] = {0.0, 0.0, 0.0};
     double p[QMAX];
     for (int a = 0; a < L->d; a++) {
@@ -172,12 +191,25 @@ static void feq_entropic(const lattice_t *L, double rho, const double *u, double
         solve_small(L->d, C, r, db);
         for (int a = 0; a < L->d; a++) b[a] -= db[a];
     }
-    double Z = 0.0;
+    double em1[QMAX], zm1 = 0.0;
     for (int i = 0; i < L->q; i++) {
-        p[i] = L->w[i] * exp(b[0] * L->e[i][0] + b[1] * L->e[i][1] + b[2] * L->e[i][2]);
-        Z += p[i];
+        em1[i] = expm1(b[0] * L->e[i][0] + b[1] * L->e[i][1] + b[2] * L->e[i][2]);
+        zm1 += L->w[i] * em1[i];
     }
-    for (int i = 0; i < L->q; i++) feq[i] = rho * p[i] / Z;
+    for (int i = 0; i < L->q; i++) dp[i] = L->w[i] * (em1[i] - zm1) / (1.0 + zm1);
+}
+
+static void feq_entropic(const lattice_t *L, double rho, const double *u, double *feq) {
+    double dp[QMAX];
+    entropic_dp(L, u, dp);
+    for (int i = 0; i < L->q; i++) feq[i] = rho * (L->w[i] + dp[i]);
+}
+
+/* entropic equilibrium minus the rest weights: rho dp_i + drho w_i */
+static void heq_entropic(const lattice_t *L, double drho, const double *u, double *heq) {
+    double dp[QMAX];
+    entropic_dp(L, u, dp);
+    for (int i = 0; i < L->q; i++) heq[i] = (1.0 + drho) * dp[i] + drho * L->w[i];
 }
 
 void orc_feq_entropic(int lattice, double rho, const double *u, double *feq) {
@@ -278,12 +310,12 @@ static void g_dg(int q, const double *f, const double *D, double a, double *g, d
     *dg = ds;
 }
 
-void orc_alpha_features(int lattice, const double *f, const double *feq, double rho, double vsq,
-                        double *feat) {
-    int q = orc_q(lattice);
+/* The six MLP inputs: log10(a2/rho), a3/a2, a4/a2, max(-d), max(d), |v|^2/c_s^2 with
+ * d_i = D_i/f_i and a_k = sum_i f_i d_i^k. */
+static void alpha_features(int q, const double *f, const double *D, double rho, double vsq, double *feat) {
     double a2 = 0, a3 = 0, a4 = 0, mneg = -1e300, mpos = -1e300;
     for (int i = 0; i < q; i++) {
-        double d = (feq[i] - f[i]) / f[i];
+        double d = D[i] / f[i];
         a2 += f[i] * d * d;
         a3 += f[i] * d * d * d;
         a4 += f[i] * d * d * d * d;
@@ -296,6 +328,14 @@ void orc_alpha_features(int lattice, const double *f, const double *feq, double 
     feat[3] = mneg;
     feat[4] = mpos;
     feat[5] = 3.0 * vsq;
+}
+
+void orc_alpha_features(int lattice, const double *f, const double *feq, double rho, double vsq,
+                        double *feat) {
+    int q = orc_q(lattice);
+    double D[QMAX];
+    for (int i = 0; i < q; i++) D[i] = feq[i] - f[i];
+    alpha_features(q, f, D, rho, vsq, feat);
 }
 
 /* MLP 6 -> 32 -> 32 -> 1, tanh hidden layers, output 2 + linear.
@@ -369,13 +409,12 @@ double orc_mlp_loss_grad(const double *p, const double *x, const double *t, int6
  * safeguarded Newton iteration: the bracket starts at [1, alpha_max) where
  * g(1) = H(feq) - H(f) <= 0 and alpha_max keeps every population positive;
  * stop when the Newton step |d alpha| <= tol, otherwise a Newton iterate
- * outside the bracket is replaced by the bracket's midpoint.  No convergence within maxit: alpha = min(2, 0.99 alpha_max). */
-double orc_alpha(int lattice, const double *f, const double *feq, int init, const double *mlp,
-                 double vsq, double tol, int maxit, int *iters, int *converged) {
-    int q = orc_q(lattice);
-    double D[QMAX], dmax = 0.0, amax = INFINITY;
+ * outside the bracket is replaced by the bracket's midpoint.  No convergence within
+ * maxit: alpha = min(2, 0.99 alpha_max).  f = populations, D = feq - f. */
+static double alpha_solve(int q, const double *f, const double *D, int init, const double *mlp, double rho,
+                          double vsq, double tol, int maxit, int *iters, int *converged) {
+    double dmax = 0.0, amax = INFINITY;
     for (int i = 0; i < q; i++) {
-        D[i] = feq[i] - f[i];
         double r = fabs(D[i] / f[i]);
         if (r > dmax) dmax = r;
         if (D[i] < 0.0 && -f[i] / D[i] < amax) amax = -f[i] / D[i];
@@ -395,9 +434,8 @@ double orc_alpha(int lattice, const double *f, const double *feq, int init, cons
         }
         a0 = 2.0 + (a3 - 2.0 * a4) / (3.0 * a2);
     } else if (init == 2 && mlp) {
-        double feat[MLP_IN], h1[MLP_H], h2[MLP_H], rho = 0.0;
-        for (int i = 0; i < q; i++) rho += f[i];
-        orc_alpha_features(lattice, f, feq, rho, vsq, feat);
+        double feat[MLP_IN], h1[MLP_H], h2[MLP_H];
+        alpha_features(q, f, D, rho, vsq, feat);
         a0 = mlp_eval(mlp, feat, h1, h2);
     }
     double lo = 1.0, hi = amax, a = a0;
@@ -423,6 +461,17 @@ double orc_alpha(int lattice, const double *f, const double *feq, int init, cons
     return amax * 0.99 < 2.0 ? amax * 0.99 : 2.0;
 }
 
+double orc_alpha(int lattice, const double *f, const double *feq, int init, const double *mlp,
+                 double vsq, double tol, int maxit, int *iters, int *converged) {
+    int q = orc_q(lattice);
+    double D[QMAX], rho = 0.0;
+    for (int i = 0; i < q; i++) {
+        D[i] = feq[i] - f[i];
+        rho += f[i];
+    }
+    return alpha_solve(q, f, D, init, mlp, rho, vsq, tol, maxit, iters, converged);
+}
+
 /* ---- collision ---------------------------------------------------------------- */
 
 /* Guo source term without its (1 - 1/(2 tau)) prefactor (body forces section):
@@ -436,62 +485,73 @@ static void guo_source(const lattice_t *L, const double *v, const double *F, dou
     }
 }
 
-static void moments(const lattice_t *L, const double *f, double *rho, double *j) {
+/* Moments of the deviations h = f - w: drho = sum h (so rho = 1 + drho) and
+ * j = sum e h (= sum e f because sum w e = 0). */
+static void moments(const lattice_t *L, const double *h, double *drho, double *j) {
     double r = 0.0;
     j[0] = j[1] = j[2] = 0.0;
     for (int i = 0; i < L->q; i++) {
-        r += f[i];
-        for (int a = 0; a < 3; a++) j[a] += L->e[i][a] * f[i];
+        r += h[i];
+        for (int a = 0; a < 3; a++) j[a] += L->e[i][a] * h[i];
     }
-    *rho = r;
+    *drho = r;
 }
 
 typedef struct {
     int iters, converged;
 } node_info;
 
-/* One fluid node's collision for BGK, MRT or ELBM. */
-static void collide_single(const orc_params *P, const lattice_t *L, const double *f, double *out,
+/* One fluid node's collision for BGK, MRT or ELBM, on the deviations h = f - w (the
+ * round-off minimising formulation of the precision subsection; every operation
+ * below is linear in f or uses f = w + h explicitly, so it is the same update). */
+static void collide_single(const orc_params *P, const lattice_t *L, const double *h, double *out,
                            node_info *info) {
     int q = L->q;
-    double rho, j[3], F[3], v[3], feq[QMAX];
-    moments(L, f, &rho, j);
+    double drho, rho, j[3], F[3], v[3], heq[QMAX];
+    moments(L, h, &drho, j);
+    rho = 1.0 + drho;
     if (P->model == ORC_ELBM) {
+        double f[QMAX], D[QMAX];
         for (int a = 0; a < 3; a++) v[a] = j[a] / rho;
-        feq_entropic(L, rho, v, feq);
+        heq_entropic(L, drho, v, heq);
+        for (int i = 0; i < q; i++) {
+            f[i] = L->w[i] + h[i];
+            D[i] = heq[i] - h[i];
+        }
         double vsq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         int it, conv;
-        double alpha = orc_alpha(P->lattice, f, feq, P->alpha_init, P->mlp, vsq, P->alpha_tol,
-                                 P->alpha_maxit, &it, &conv);
+        double alpha = alpha_solve(q, f, D, P->alpha_init, P->mlp, rho, vsq, P->alpha_tol, P->alpha_maxit,
+                                   &it, &conv);
         if (info) {
             info->iters = it;
             info->converged = conv;
         }
         double beta = 1.0 / (2.0 * P->tau);
-        for (int i = 0; i < q; i++) out[i] = f[i] + alpha * beta * (feq[i] - f[i]);
+        for (int i = 0; i < q; i++) out[i] = h[i] + alpha * beta * D[i];
         return;
     }
     for (int a = 0; a < 3; a++) {
         F[a] = rho * P->g[a];
         v[a] = (j[a] + 0.5 * F[a]) / rho;
     }
-    feq_poly(L, rho, v, feq);
+    heq_poly(L, drho, v, heq);
     double Fi[QMAX];
     guo_source(L, v, F, Fi);
     if (P->model == ORC_BGK) {
         double omega = 1.0 / P->tau, pre = 1.0 - 1.0 / (2.0 * P->tau);
-        for (int i = 0; i < q; i++) out[i] = f[i] + omega * (feq[i] - f[i]) + pre * Fi[i];
+        for (int i = 0; i < q; i++) out[i] = h[i] + omega * (heq[i] - h[i]) + pre * Fi[i];
         return;
     }
-    /* MRT: m = M f, m* = m - S (m - m_eq) + (I - S/2) M F~, f* = M^-1 m*,
-     * with M^-1 = M^T diag(1/|row|^2) for the orthogonal basis. */
+    /* MRT: m = M h, m* = m - S (m - m_eq) + (I - S/2) M F~, h* = M^-1 m*,
+     * with M^-1 = M^T diag(1/|row|^2) for the orthogonal basis (linear, so the same
+     * as relaxing f with m_eq = M feq). */
     double M[QMAX][QMAX], n2[QMAX], m[QMAX], meq[QMAX], mF[QMAX], ms[QMAX];
     mrt_build(P->lattice, L, M, n2);
     for (int k = 0; k < q; k++) {
         m[k] = meq[k] = mF[k] = 0.0;
         for (int i = 0; i < q; i++) {
-            m[k] += M[k][i] * f[i];
-            meq[k] += M[k][i] * feq[i];
+            m[k] += M[k][i] * h[i];
+            meq[k] += M[k][i] * heq[i];
             mF[k] += M[k][i] * Fi[i];
         }
         ms[k] = m[k] - P->s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * P->s[k]) * mF[k];
@@ -505,8 +565,11 @@ static void collide_single(const orc_params *P, const lattice_t *L, const double
 
 void orc_collide_node(const orc_params *P, const double *f, double *out) {
     lattice_t L;
+    double h[QMAX], o[QMAX];
     make_lattice(P->lattice, &L);
-    collide_single(P, &L, f, out, NULL);
+    for (int i = 0; i < L.q; i++) h[i] = f[i] - L.w[i];
+    collide_single(P, &L, h, o, NULL);
+    for (int i = 0; i < L.q; i++) out[i] = L.w[i] + o[i];
 }
 
 /* ---- full-lattice operations ------------------------------------------------------ */
@@ -554,20 +617,23 @@ int orc_init_eq(const orc_params *P, const double *rho, const double *u, const d
     int C = P->model == ORC_SHANCHEN ? 2 : 1;
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
-        double uu[3] = {0, 0, 0}, feq[QMAX];
+        double uu[3] = {0, 0, 0}, heq[QMAX];
         for (int a = 0; a < L.d; a++) uu[a] = u[a * N + n];
         for (int c = 0; c < C; c++) {
-            if (P->model == ORC_ELBM) feq_entropic(&L, rho[c * N + n], uu, feq);
-            else feq_poly(&L, rho[c * N + n], uu, feq);
+            double drho = rho[c * N + n] - 1.0;
+            if (P->model == ORC_ELBM) heq_entropic(&L, drho, uu, heq);
+            else heq_poly(&L, drho, uu, heq);
             for (int i = 0; i < L.q; i++) {
                 int64_t k = ((int64_t)c * L.q + i) * N + n;
-                f[k] = feq[i] + (df ? df[k] : 0.0);
+                f[k] = L.w[i] + (heq[i] + (df ? df[k] : 0.0));
             }
         }
     }
     return 0;
 }
 
+/* Runs `steps` time steps on f (canonical populations, updated in place).  The state is
+ * carried as h = f - w during the run and converted back at the end. */
 int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc_stats *st) {
     if (check_params(P) || steps < 0) return -1;
     lattice_t L;
@@ -578,44 +644,44 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
     if (C == 2 && flags)
         for (int64_t n = 0; n < N; n++)
             if (flags[n]) return -2; /* walls are not defined for the two-component model */
-    double *cur = f;
+    double *cur = (double *)malloc(sizeof(double) * C * q * N);
     double *nxt = (double *)malloc(sizeof(double) * C * q * N);
-    double *rho_all = C == 2 ? (double *)malloc(sizeof(double) * 2 * N) : NULL;
     double *psi = C == 2 ? (double *)malloc(sizeof(double) * 2 * N) : NULL;
-    if (!nxt || (C == 2 && (!rho_all || !psi))) {
+    if (!cur || !nxt || (C == 2 && !psi)) {
+        free(cur);
         free(nxt);
-        free(rho_all);
         free(psi);
         return -3;
     }
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < (int64_t)C * q * N; k++) cur[k] = f[k] - L.w[(k / N) % q];
     int64_t hist[32] = {0}, noconv = 0, nodes = 0;
 
     for (int t = 0; t < steps; t++) {
         if (C == 2) {
-            /* macroscopic pre-pass: every node's density and pseudopotential at time t */
+            /* macroscopic pre-pass: every node's pseudopotential at time t */
 #pragma omp parallel for schedule(static)
             for (int64_t n = 0; n < N; n++)
                 for (int c = 0; c < 2; c++) {
                     double r = 0.0;
                     for (int i = 0; i < q; i++) r += cur[((int64_t)c * q + i) * N + n];
-                    rho_all[c * N + n] = r;
-                    psi[c * N + n] = psi_of(P, r);
+                    psi[c * N + n] = psi_of(P, 1.0 + r);
                 }
         }
 #pragma omp parallel for schedule(static) reduction(+ : noconv, nodes)
         for (int64_t n = 0; n < N; n++) {
             int64_t x = n % P->nx, y = (n / P->nx) % P->ny, z = n / ((int64_t)P->nx * P->ny);
-            double fl[2][QMAX], post[2][QMAX];
+            double hl[2][QMAX], post[2][QMAX];
             for (int c = 0; c < C; c++)
-                for (int i = 0; i < q; i++) fl[c][i] = cur[((int64_t)c * q + i) * N + n];
+                for (int i = 0; i < q; i++) hl[c][i] = cur[((int64_t)c * q + i) * N + n];
             if (flags && flags[n] == 1) {
                 /* full-way bounce-back: a wall node returns each population along the
-                 * opposite direction instead of colliding */
+                 * opposite direction instead of colliding (w_i = w_opp(i), so the same on h) */
                 for (int c = 0; c < C; c++)
-                    for (int i = 0; i < q; i++) post[c][i] = fl[c][L.opp[i]];
+                    for (int i = 0; i < q; i++) post[c][i] = hl[c][L.opp[i]];
             } else if (C == 1) {
                 node_info info = {0, 1};
-                collide_single(P, &L, fl[0], post[0], &info);
+                collide_single(P, &L, hl[0], post[0], &info);
                 if (P->model == ORC_ELBM) {
                     int b = info.iters < 31 ? info.iters : 31;
 #pragma omp atomic
@@ -625,21 +691,22 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
                 }
             } else {
                 /* Shan-Chen with EDM forcing around the common velocity */
-                double rc[2], jc[2][3], Fc[2][3], up[3], num[3] = {0, 0, 0}, den = 0.0;
+                double dr[2], rc[2], jc[2][3], Fc[2][3], up[3], num[3] = {0, 0, 0}, den = 0.0;
                 for (int c = 0; c < 2; c++) {
-                    moments(&L, fl[c], &rc[c], jc[c]);
+                    moments(&L, hl[c], &dr[c], jc[c]);
+                    rc[c] = 1.0 + dr[c];
                     sc_force(P, &L, psi, N, x, y, z, c, rc[c], Fc[c]);
                     for (int a = 0; a < 3; a++) num[a] += jc[c][a] / P->tau;
                     den += rc[c] / P->tau;
                 }
                 for (int a = 0; a < 3; a++) up[a] = num[a] / den;
                 for (int c = 0; c < 2; c++) {
-                    double f0[QMAX], f1[QMAX], u1[3];
+                    double h0[QMAX], h1[QMAX], u1[3];
                     for (int a = 0; a < 3; a++) u1[a] = up[a] + Fc[c][a] / rc[c];
-                    feq_poly(&L, rc[c], up, f0);
-                    feq_poly(&L, rc[c], u1, f1);
+                    heq_poly(&L, dr[c], up, h0);
+                    heq_poly(&L, dr[c], u1, h1);
                     for (int i = 0; i < q; i++)
-                        post[c][i] = fl[c][i] + (f0[i] - fl[c][i]) / P->tau + (f1[i] - f0[i]);
+                        post[c][i] = hl[c][i] + (h0[i] - hl[c][i]) / P->tau + (h1[i] - h0[i]);
                 }
             }
             /* propagation: the value leaving node x along e_i lands on x + e_i */
@@ -652,12 +719,10 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
         cur = nxt;
         nxt = tmp;
     }
-    if (cur != f) {
-        memcpy(f, cur, sizeof(double) * C * q * N);
-        nxt = cur;
-    }
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < (int64_t)C * q * N; k++) f[k] = L.w[(k / N) % q] + cur[k];
+    free(cur);
     free(nxt);
-    free(rho_all);
     free(psi);
     if (st) {
         for (int b = 0; b < 32; b++) st->newton_hist[b] += hist[b];
@@ -681,17 +746,18 @@ int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double
         for (int64_t n = 0; n < N; n++)
             for (int c = 0; c < 2; c++) {
                 double r = 0.0;
-                for (int i = 0; i < q; i++) r += f[((int64_t)c * q + i) * N + n];
-                psi[c * N + n] = psi_of(P, r);
+                for (int i = 0; i < q; i++) r += f[((int64_t)c * q + i) * N + n] - L.w[i];
+                psi[c * N + n] = psi_of(P, 1.0 + r);
             }
     }
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
         int64_t x = n % P->nx, y = (n / P->nx) % P->ny, z = n / ((int64_t)P->nx * P->ny);
-        double rc[2], jc[2][3], fl[QMAX];
+        double rc[2], jc[2][3], hl[QMAX], dr;
         for (int c = 0; c < C; c++) {
-            for (int i = 0; i < q; i++) fl[i] = f[((int64_t)c * q + i) * N + n];
-            moments(&L, fl, &rc[c], jc[c]);
+            for (int i = 0; i < q; i++) hl[i] = f[((int64_t)c * q + i) * N + n] - L.w[i];
+            moments(&L, hl, &dr, jc[c]);
+            rc[c] = 1.0 + dr;
             rho[c * N + n] = rc[c];
         }
         double v[3] = {0, 0, 0};

@@ -82,7 +82,8 @@ def test_wall_node_swaps_and_streams():
     o.run(1)
     for i in range(9):
         x, y = (2 + e[i][0]) % 5, (2 + e[i][1]) % 5
-        assert o.f[0, i, x + 5 * y] == f[0, opp[i], 12]
+        # the swap itself is exact; the oracle's f -> f - w -> f conversion rounds once
+        assert abs(o.f[0, i, x + 5 * y] - f[0, opp[i], 12]) <= 2.8e-17
 
 
 # --------------------------------------------------------------------------- P2
@@ -544,8 +545,9 @@ def test_shan_chen_component_momentum_closed_form():
         o.run(1)
         pA, pB = (np.einsum("qn,qa->a", o.f[c], e) for c in (0, 1))
         sc = G / 3 * eps ** 2 * np.sin(k) * n / 2 * 4
-        np.testing.assert_allclose(pA[0], -sc + gx * rho[0].sum(), rtol=1e-11)
-        np.testing.assert_allclose(pB[0], sc + gx * rho[1].sum(), rtol=1e-11)
+        # summing e.f over 64 x 19 populations of size ~w rounds at ~1e-14 absolute
+        np.testing.assert_allclose(pA[0], -sc + gx * rho[0].sum(), rtol=1e-11, atol=2e-14)
+        np.testing.assert_allclose(pB[0], sc + gx * rho[1].sum(), rtol=1e-11, atol=2e-14)
         assert np.abs(pA[1:]).max() < 1e-16 and np.abs(pB[1:]).max() < 1e-16
 
 
