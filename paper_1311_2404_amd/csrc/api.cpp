@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -18,6 +19,7 @@ using namespace lbm;
 struct lbm_sim {
     int lattice = 0, model = 0, nx = 0, ny = 0, nz = 0, Q = 0, D = 0, C = 1;
     uint32_t N = 0;
+    uint32_t S = 0;  // population stride (elements), fixed at allocation
     double tau = 1.0, g[3] = {0, 0, 0};
     int storage = LBM_F32, layout = LBM_AB, sr = 0;
     double s[19] = {0};
@@ -116,6 +118,7 @@ StepParams base_params(const lbm_sim *s) {
     p.ny = s->ny;
     p.nz = s->nz;
     p.N = s->N;
+    p.S = s->S;
     p.flags = s->has_walls ? s->flags_d : nullptr;
     p.omega = 1.0 / s->tau;
     for (int a = 0; a < 3; a++) p.g[a] = s->g[a];
@@ -134,10 +137,24 @@ StepParams base_params(const lbm_sim *s) {
     return p;
 }
 
+// Population stride: N rounded up to whole 256-byte rows plus a pad, so that the Q
+// population arrays do not start at addresses that differ by a large power of two
+// (which would map the 2Q streams of a row onto the same HBM channels).  The pad can be
+// overridden with the LBM_POP_PAD environment variable (elements).
+uint32_t pop_stride(const lbm_sim *s) {
+    const uint64_t align = 256 / elem_size(s->storage);
+    uint64_t S = (uint64_t(s->N) + align - 1) / align * align;
+    uint64_t pad = 0;
+    if (const char *e = std::getenv("LBM_POP_PAD")) pad = std::strtoull(e, nullptr, 10) / align * align;
+    S += pad;
+    return S >= (uint64_t(1) << 32) ? s->N : uint32_t(S);
+}
+
 int ensure_alloc(lbm_sim *s) {
     if (s->ready) return LBM_OK;
     HIPCHK(s, hipSetDevice(s->device));
-    const size_t bytes = size_t(s->C) * s->Q * s->N * elem_size(s->storage);
+    s->S = pop_stride(s);
+    const size_t bytes = size_t(s->C) * s->Q * s->S * elem_size(s->storage);
     HIPCHK(s, hipMalloc(&s->buf[0], bytes));
     if (s->layout == LBM_AB) HIPCHK(s, hipMalloc(&s->buf[1], bytes));
     HIPCHK(s, hipMalloc(&s->stage, sizeof(double) * s->N));
@@ -165,6 +182,7 @@ PlaneParams plane_params(const lbm_sim *s, int layout, int c, int q) {
     p.ny = s->ny;
     p.nz = s->nz;
     p.N = s->N;
+    p.S = s->S;
     p.layout = layout;
     p.comp = c;
     p.q = q;
@@ -191,6 +209,7 @@ int macro_into(lbm_sim *s, void *rho, void *u, int fp64, unsigned int *bad) {
     m.ny = s->ny;
     m.nz = s->nz;
     m.N = s->N;
+    m.S = s->S;
     m.layout = state_layout(s);
     m.model = s->model;
     m.ncomp = s->C;

@@ -63,10 +63,10 @@ __global__ void k_init_plane(PlaneParams p) {
 #pragma unroll
     for (int i = 0; i < L::Q; i++)
         if (i == p.q) w = L::w(i);
-    T *pop = static_cast<T *>(p.pop) + size_t(p.comp) * L::Q * p.N;
+    T *pop = static_cast<T *>(p.pop) + size_t(p.comp) * L::Q * p.S;
     // unshifted storages round f = w + h once; shifted ones round h
-    if constexpr (St::shifted) pop[size_t(slot) * p.N + nd] = St::encode(C(h), C(w), 0u);
-    else pop[size_t(slot) * p.N + nd] = T(w + h);
+    if constexpr (St::shifted) pop[size_t(slot) * p.S + nd] = St::encode(C(h), C(w), 0u);
+    else pop[size_t(slot) * p.S + nd] = T(w + h);
 }
 
 template <class L, class St>
@@ -83,8 +83,8 @@ __global__ void k_get_plane(PlaneParams p) {
 #pragma unroll
     for (int i = 0; i < L::Q; i++)
         if (i == p.q) w = L::w(i);
-    const T *pop = static_cast<const T *>(p.pop) + size_t(p.comp) * L::Q * p.N;
-    const T v = pop[size_t(slot) * p.N + nd];
+    const T *pop = static_cast<const T *>(p.pop) + size_t(p.comp) * L::Q * p.S;
+    const T v = pop[size_t(slot) * p.S + nd];
     if constexpr (St::shifted) p.plane[n] = w + double(St::decode(v, C(w)));
     else p.plane[n] = double(v);
 }
@@ -103,9 +103,9 @@ __global__ void k_set_plane(PlaneParams p) {
 #pragma unroll
     for (int i = 0; i < L::Q; i++)
         if (i == p.q) w = L::w(i);
-    T *pop = static_cast<T *>(p.pop) + size_t(p.comp) * L::Q * p.N;
-    if constexpr (St::shifted) pop[size_t(slot) * p.N + nd] = St::encode(C(p.plane[n] - w), C(w), 0u);
-    else pop[size_t(slot) * p.N + nd] = T(p.plane[n]);
+    T *pop = static_cast<T *>(p.pop) + size_t(p.comp) * L::Q * p.S;
+    if constexpr (St::shifted) pop[size_t(slot) * p.S + nd] = St::encode(C(p.plane[n] - w), C(w), 0u);
+    else pop[size_t(slot) * p.S + nd] = T(p.plane[n]);
 }
 
 // Macroscopic output.  Density per component; velocity (j + F/2)/rho for the forced
@@ -119,14 +119,14 @@ __global__ void k_macro(MacroParams p) {
     const Geo g = geo_of(n, p.nx, p.ny, p.nz);
     double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
     for (int c = 0; c < p.ncomp; c++) {
-        const T *pop = static_cast<const T *>(p.pop) + size_t(c) * L::Q * p.N;
+        const T *pop = static_cast<const T *>(p.pop) + size_t(c) * L::Q * p.S;
         C h[L::Q];
 #pragma unroll
         for (int i = 0; i < L::Q; i++) {
             int slot;
             uint32_t nd;
             canon_loc<L>(p.layout, i, g, slot, nd);
-            h[i] = St::decode(pop[size_t(slot) * p.N + nd], C(L::w(i)));
+            h[i] = St::decode(pop[size_t(slot) * p.S + nd], C(L::w(i)));
         }
         const Macro<C> m = moments<L, C>(h);
         rho[c] = double(m.rho);

@@ -66,6 +66,7 @@ hipError_t launch_psi(int lattice, int storage, int layout, const StepParams &p,
 struct PlaneParams {
     int nx, ny, nz;
     uint32_t N;
+    uint32_t S;        // population stride (elements)
     int layout;        // LAYOUT_* of the state being accessed
     int comp, q;       // component and population index of the plane
     void *pop;         // population array (all components)
@@ -82,6 +83,7 @@ hipError_t launch_set_plane(int lattice, int storage, const PlaneParams &p, cons
 struct MacroParams {
     int nx, ny, nz;
     uint32_t N;
+    uint32_t S;        // population stride (elements)
     int layout, model, ncomp;
     const void *pop;
     const uint8_t *flags;

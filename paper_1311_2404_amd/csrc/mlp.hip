@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_alpha_dataset(MlpDatasetParams d) {
         int slot;
         uint32_t nd;
         canon_loc<L>(d.layout, i, g, slot, nd);
-        h[i] = St::decode(src[size_t(slot) * p.N + nd], C(L::w(i)));
+        h[i] = St::decode(src[size_t(slot) * p.S + nd], C(L::w(i)));
     }
     const Macro<C> m = moments<L, C>(h);
     const C irho = C(1) / m.rho;

@@ -16,6 +16,8 @@ constexpr int NEWTON_BINS = 32;
 struct StepParams {
     int nx, ny, nz;
     uint32_t N;                 // nodes per component
+    uint32_t S;                 // population stride in elements (>= N; padding spreads the
+                                // Q streams of a row over HBM channels)
     const void *src;            // populations read (AB: current copy; AA: the single copy)
     void *dst;                  // populations written (AB: the other copy; AA: == src)
     const uint8_t *flags;       // node flags or nullptr

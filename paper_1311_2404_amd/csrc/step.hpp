@@ -24,6 +24,19 @@
 #include "params.hpp"
 #include "storage.hpp"
 
+// Population loads and stores of the step kernels.  Build-time variants (non-temporal
+// hints) are selected by LBM_NT_LOADS / LBM_NT_STORES.
+#if defined(LBM_NT_LOADS)
+#define LBM_LOAD(ptr) __builtin_nontemporal_load(ptr)
+#else
+#define LBM_LOAD(ptr) (*(ptr))
+#endif
+#if defined(LBM_NT_STORES)
+#define LBM_STORE(ptr, v) __builtin_nontemporal_store((v), (ptr))
+#else
+#define LBM_STORE(ptr, v) (*(ptr) = (v))
+#endif
+
 namespace lbm {
 
 struct Geo {
@@ -112,7 +125,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     if (active) {
         const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
         const uint32_t n = g.at(0, 0, 0);
-        const uint32_t N = p.N;
+        const uint32_t S = p.S;
         // no __restrict__: with AA the two pointers are the same copy
         const T *src = static_cast<const T *>(p.src);
         T *dst = static_cast<T *>(p.dst);
@@ -122,7 +135,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             int slot;
             uint32_t nd;
             canon_loc<L>(LAYOUT, i, g, slot, nd);
-            raw[i] = src[size_t(slot) * N + nd];
+            raw[i] = LBM_LOAD(src + size_t(slot) * S + nd);
         }
         T out[Q];
         const bool wall = FLAGS && p.flags[n] == 1;
@@ -156,6 +169,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                 const C ab = C(ao.alpha * p.beta);
 #pragma unroll
                 for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
+                conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
                 if (p.stats) {
                     atomicAdd(&s_hist[ao.iters < NEWTON_BINS ? ao.iters : NEWTON_BINS - 1], 1u);
                     if (!ao.converged) atomicAdd(&s_hist[NEWTON_BINS], 1u);
@@ -175,7 +189,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             int slot;
             uint32_t nd;
             post_loc<L>(LAYOUT, i, g, slot, nd);
-            dst[size_t(slot) * N + nd] = out[i];
+            LBM_STORE(dst + size_t(slot) * S + nd, out[i]);
         }
     }
     if constexpr (MODEL == M_ELBM) {
@@ -203,14 +217,14 @@ __global__ __launch_bounds__(512) void k_psi(StepParams p) {
     C *psi = static_cast<C *>(const_cast<void *>(p.psi));
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-        const T *fc = src + size_t(c) * L::Q * p.N;
+        const T *fc = src + size_t(c) * L::Q * p.S;
         C r = C(0);
 #pragma unroll
         for (int i = 0; i < L::Q; i++) {
             int slot;
             uint32_t nd;
             canon_loc<L>(LAYOUT, i, g, slot, nd);
-            r += St::decode(fc[size_t(slot) * p.N + nd], C(L::w(i)));
+            r += St::decode(fc[size_t(slot) * p.S + nd], C(L::w(i)));
         }
         const C rho = C(1) + r;
         psi[size_t(c) * p.N + n] = p.psi_mode == 1 ? C(1) - exp(-rho) : rho;
@@ -230,7 +244,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
     if (x >= p.nx || y >= p.ny) return;
     const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
     const uint32_t n = g.at(0, 0, 0);
-    const uint32_t N = p.N;
+    const uint32_t N = p.N, S = p.S;
     const T *src = static_cast<const T *>(p.src);
     T *dst = static_cast<T *>(p.dst);
     const C *__restrict__ psi = static_cast<const C *>(p.psi);
@@ -244,7 +258,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
             int slot;
             uint32_t nd;
             canon_loc<L>(LAYOUT, i, g, slot, nd);
-            h[c][i] = St::decode(src[(size_t(c) * Q + slot) * N + nd], C(L::w(i)));
+            h[c][i] = St::decode(LBM_LOAD(src + (size_t(c) * Q + slot) * S + nd), C(L::w(i)));
         }
         m[c] = moments<L, C>(h[c]);
     }
@@ -277,6 +291,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
         const C dx = F[c][0] * ir, dy = F[c][1] * ir, dz = F[c][2] * ir;
         // feq(rho, u + du) - feq(rho, u) expanded so that it carries no cancellation
         const C du15 = C(1.5) * (dx * (C(2) * ux + dx) + dy * (C(2) * uy + dy) + dz * (C(2) * uz + dz));
+        C o[Q];
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             const C w = C(L::w(i));
@@ -284,13 +299,20 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
             const C ed = C(L::ex(i)) * dx + C(L::ey(i)) * dy + C(L::ez(i)) * dz;
             const C heq = w * (m[c].drho + m[c].rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
             const C edm = w * m[c].rho * (C(3) * ed + C(4.5) * ed * (C(2) * eu + ed) - du15);
-            const C o = h[c][i] + omega * (heq - h[c][i]) + edm;
+            o[i] = h[c][i] + omega * (heq - h[c][i]) + edm;
+        }
+        // component momentum after relaxation towards rho_c u' plus the EDM kick F_c
+        conserve<L, C>(o, m[c].drho, m[c].jx + omega * (m[c].rho * ux - m[c].jx) + F[c][0],
+                       m[c].jy + omega * (m[c].rho * uy - m[c].jy) + F[c][1],
+                       m[c].jz + omega * (m[c].rho * uz - m[c].jz) + F[c][2]);
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
             uint32_t rnd = 0;
             if constexpr (sizeof(T) == 2) rnd = hash32(((n * 19u + uint32_t(i)) * 2u + uint32_t(c)) ^ key);
             int slot;
             uint32_t nd;
             post_loc<L>(LAYOUT, i, g, slot, nd);
-            dst[(size_t(c) * Q + slot) * N + nd] = St::encode(o, w, rnd);
+            LBM_STORE(dst + (size_t(c) * Q + slot) * S + nd, St::encode(o[i], C(L::w(i)), rnd));
         }
     }
 }

@@ -52,8 +52,10 @@ def check_f64(case, steps, layouts=(P.LBM_AB, P.LBM_AA), tol=1e-12, elbm=None, o
     for lay in layouts:
         fg, rg, ug = gpu_run(case, steps, P.LBM_F64, lay, elbm=elbm)
         assert rel(fg - w, fo - w) <= tol, (case.name, lay, rel(fg - w, fo - w))
-        assert rel(rg - 1, ro - 1) <= tol
         assert rel(ug, uo) <= tol, (case.name, lay, rel(ug, uo))
+        # density: rho - 1 can be zero to rounding (channel flows), so its deviation is
+        # compared with an absolute floor of 1e-15 relative to rho itself
+        assert np.linalg.norm(rg - ro) <= tol * np.linalg.norm(ro - 1) + 1e-15 * np.linalg.norm(ro)
 
 
 def random_case(lattice, model, nx, ny, nz, tau=0.7, force=(0, 0, 0), walls=False, seed=1, du=0.05, drho=0.02,
@@ -206,7 +208,9 @@ def test_set_get_roundtrip_all_storages():
             w = weights(S.D3Q19)[None, :, None]
             ref = (o.f - w) if st in (P.LBM_F32S, P.LBM_BF16S, P.LBM_F16S) else o.f
             got = (g - w) if st in (P.LBM_F32S, P.LBM_BF16S, P.LBM_F16S) else g
-            assert np.all(np.abs(got - ref) <= tol * np.abs(ref) + 1e-300), (st, lay)
+            # half a unit in the last place, relative; IEEE half has subnormals below 2^-14
+            floor = 2.0 ** -25 if st == P.LBM_F16S else 1e-300
+            assert np.all(np.abs(got - ref) <= np.maximum(tol * np.abs(ref), floor)), (st, lay)
             s.close()
 
 
