@@ -69,6 +69,7 @@ def lib():
         L.orc_mlp_loss_grad.argtypes = [dp, dp, dp, C.c_int64, dp]
         L.orc_mlp_loss_grad.restype = C.c_double
         L.orc_collide_node.argtypes = [P, dp, dp]
+        L.orc_collide_node_sc.argtypes = [P, dp, dp, dp]
         L.orc_init_eq.argtypes = [P, dp, dp, dp, dp]
         L.orc_run.argtypes = [P, C.c_void_p, dp, C.c_int, C.POINTER(Stats)]
         L.orc_macro.argtypes = [P, C.c_void_p, dp, dp, dp]
@@ -207,6 +208,12 @@ class Oracle:
     def collide_node(self, fnode):
         out = np.zeros(self.q)
         lib().orc_collide_node(C.byref(self.p), _dp(_f64(fnode)), _dp(out))
+        return out
+
+    def collide_node_sc(self, f2, psi_nb):
+        """f2[2][q] populations at x, psi_nb[2][q] pseudopotential at x + e_i."""
+        out = np.zeros((2, self.q))
+        lib().orc_collide_node_sc(C.byref(self.p), _dp(_f64(f2)), _dp(_f64(psi_nb)), _dp(out))
         return out
 
     def run(self, steps):

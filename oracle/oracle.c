@@ -572,6 +572,39 @@ void orc_collide_node(const orc_params *P, const double *f, double *out) {
     for (int i = 0; i < L.q; i++) out[i] = L.w[i] + o[i];
 }
 
+/* One Shan-Chen node: f2[2][q] the populations of both components at x, psi_nb[2][q]
+ * psi of each component at x + e_i (psi_nb[c][0] = psi_c(x)).  Same update as in
+ * orc_run: force -G psi_c(x) sum_i w_i psi_other(x + e_i) e_i + rho_c g, common
+ * velocity, EDM forcing.  out2[2][q]. */
+void orc_collide_node_sc(const orc_params *P, const double *f2, const double *psi_nb, double *out2) {
+    lattice_t L;
+    make_lattice(P->lattice, &L);
+    const int q = L.q;
+    double h[2][QMAX], dr[2], rc[2], jc[2][3], Fc[2][3], up[3], num[3] = {0, 0, 0}, den = 0.0;
+    for (int c = 0; c < 2; c++) {
+        for (int i = 0; i < q; i++) h[c][i] = f2[c * q + i] - L.w[i];
+        moments(&L, h[c], &dr[c], jc[c]);
+        rc[c] = 1.0 + dr[c];
+    }
+    for (int c = 0; c < 2; c++) {
+        double s[3] = {0, 0, 0};
+        for (int i = 0; i < q; i++)
+            for (int a = 0; a < 3; a++) s[a] += L.w[i] * psi_nb[(1 - c) * q + i] * L.e[i][a];
+        for (int a = 0; a < 3; a++) Fc[c][a] = -P->G * psi_nb[c * q] * s[a] + rc[c] * P->g[a];
+        for (int a = 0; a < 3; a++) num[a] += jc[c][a] / P->tau;
+        den += rc[c] / P->tau;
+    }
+    for (int a = 0; a < 3; a++) up[a] = num[a] / den;
+    for (int c = 0; c < 2; c++) {
+        double h0[QMAX], h1[QMAX], u1[3];
+        for (int a = 0; a < 3; a++) u1[a] = up[a] + Fc[c][a] / rc[c];
+        heq_poly(&L, dr[c], up, h0);
+        heq_poly(&L, dr[c], u1, h1);
+        for (int i = 0; i < q; i++)
+            out2[c * q + i] = L.w[i] + (h[c][i] + (h0[i] - h[c][i]) / P->tau + (h1[i] - h0[i]));
+    }
+}
+
 /* ---- full-lattice operations ------------------------------------------------------ */
 
 static int check_params(const orc_params *P) {

@@ -64,6 +64,7 @@ void orc_alpha_features(int lattice, const double *f, const double *feq, double 
 void orc_mlp_forward(const double *p, const double *x, int64_t n, double *y);
 double orc_mlp_loss_grad(const double *p, const double *x, const double *t, int64_t n, double *grad);
 void orc_collide_node(const orc_params *P, const double *f, double *out);
+void orc_collide_node_sc(const orc_params *P, const double *f2, const double *psi_nb, double *out2);
 int orc_init_eq(const orc_params *P, const double *rho, const double *u, const double *df, double *f);
 int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc_stats *st);
 int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double *rho, double *u);

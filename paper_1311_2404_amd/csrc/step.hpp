@@ -24,17 +24,19 @@
 #include "params.hpp"
 #include "storage.hpp"
 
-// Population loads and stores of the step kernels.  Build-time variants (non-temporal
-// hints) are selected by LBM_NT_LOADS / LBM_NT_STORES.
+// Population loads and stores of the step kernels.  Stores carry the non-temporal hint
+// (every post-collision value is read back only in the next step, after ~2.5 GB of other
+// traffic): measured +5% on the 256^3 FP32 step.  Build variants: LBM_NT_LOADS adds the
+// hint to loads, LBM_PLAIN_STORES removes it from stores.
 #if defined(LBM_NT_LOADS)
 #define LBM_LOAD(ptr) __builtin_nontemporal_load(ptr)
 #else
 #define LBM_LOAD(ptr) (*(ptr))
 #endif
-#if defined(LBM_NT_STORES)
-#define LBM_STORE(ptr, v) __builtin_nontemporal_store((v), (ptr))
-#else
+#if defined(LBM_PLAIN_STORES)
 #define LBM_STORE(ptr, v) (*(ptr) = (v))
+#else
+#define LBM_STORE(ptr, v) __builtin_nontemporal_store((v), (ptr))
 #endif
 
 namespace lbm {
