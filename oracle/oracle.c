@@ -434,8 +434,11 @@ static double alpha_solve(int q, const double *f, const double *D, int init, con
         }
         a0 = 2.0 + (a3 - 2.0 * a4) / (3.0 * a2);
     } else if (init == 2 && mlp) {
+        /* mlp = 1313 network weights followed by the input normalisation mu[6], isd[6]:
+         * the network sees (x - mu) * isd */
         double feat[MLP_IN], h1[MLP_H], h2[MLP_H];
         alpha_features(q, f, D, rho, vsq, feat);
+        for (int k = 0; k < MLP_IN; k++) feat[k] = (feat[k] - mlp[MLP_NPARAM + k]) * mlp[MLP_NPARAM + MLP_IN + k];
         a0 = mlp_eval(mlp, feat, h1, h2);
     }
     double lo = 1.0, hi = amax, a = a0;

@@ -40,7 +40,7 @@ typedef struct {
     int alpha_init;       /* ELBM first guess: 0 -> 2, 1 -> series, 2 -> MLP */
     double alpha_tol;     /* Newton stop |d alpha| <= tol */
     int alpha_maxit;
-    const double *mlp;    /* 1313 MLP parameters (alpha_init == 2) */
+    const double *mlp;    /* alpha_init == 2: 1313 MLP weights, then mu[6], isd[6] (inputs (x-mu)*isd) */
     double G;             /* Shan-Chen coupling */
     int psi;              /* 0: psi = rho, 1: psi = 1 - exp(-rho) */
 } orc_params;
