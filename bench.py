@@ -56,6 +56,102 @@ def bytes_per_node(storage):
     return 2 * 19 * ELEM_BYTES[storage]
 
 
+def _time_steps(sim, stream, torch, steps):
+    sim.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    sim.sync()
+    return e0.elapsed_time(e1) / steps
+
+
+def run_extras(P, S, stream, torch):
+    """The other measured configurations (throughput and stated errors), one GPU."""
+    out = {}
+    # D3Q19 MRT duct 128x128x512, 5000 steps: each storage's velocity error vs FP64
+    c3 = S.c3_duct(128, 128, 512, steps=5000)
+    us, rows = {}, {}
+    for st, sr in [(P.LBM_F64, 0), (P.LBM_F32, 0), (P.LBM_F32S, 0), (P.LBM_BF16S, 0), (P.LBM_BF16S, 1),
+                   (P.LBM_F16S, 0), (P.LBM_F16S, 1)]:
+        s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
+        ms = _time_steps(s, stream, torch, 200)
+        s.close()
+        s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
+        s.step(c3.steps)
+        us[(st, sr)] = s.macro()[1]
+        s.close()
+        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")] = {"mlups": round(c3.n / ms / 1e3, 1)}
+    ref = us[(P.LBM_F64, 0)]
+    for (st, sr), u in us.items():
+        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")]["vel_rel_l2_vs_fp64"] = float(
+            np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    out["d3q19_mrt_duct_128x128x512_5000_steps"] = rows
+    print("[bench] MRT duct done", file=sys.stderr, flush=True)
+
+    # D3Q19 entropic LBM 256^3: Newton from alpha = 2 vs from the trained MLP proposal
+    c4 = S.c4_elbm_taylor_green(n=256)
+    s = P.Sim.from_case(c4, P.LBM_F32, P.LBM_AB, stream=stream)
+    feats, alphas = [], []
+    nsamp = 250000
+    for k in range(4):
+        s.step(250)
+        feat = torch.empty((nsamp, 6), dtype=torch.float32, device="cuda")
+        alpha = torch.empty(nsamp, dtype=torch.float64, device="cuda")
+        valid = torch.empty(nsamp, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        P.lbm_alpha_dataset(s.h, nsamp, 4242 + k, feat, alpha, valid)
+        s.sync()
+        keep = valid.bool()
+        feats.append(feat[keep])
+        alphas.append(alpha[keep])
+    feat = torch.cat(feats).contiguous()
+    alpha = torch.cat(alphas).contiguous()
+    torch.cuda.synchronize()  # produced on torch's stream, consumed on the library's
+    rng = np.random.default_rng(20131124)
+    p0 = (0.1 * rng.standard_normal(P.MLP_NPARAM)).astype(np.float32)
+    p0[-1] = 0.0
+    P.lbm_mlp_set_weights(s.h, p0)
+    t0 = time.perf_counter()
+    loss = P.lbm_mlp_train(s.h, feat, alpha, len(alpha), 20, 4096, 1e-3, 7) if len(alpha) else []
+    t_train = time.perf_counter() - t0
+    f0 = s.get_f()
+    elbm = {"dataset_pairs": int(len(alpha)), "train_s": round(t_train, 2),
+            "loss_first_last": [float(loss[0]), float(loss[-1])] if len(loss) else None}
+    u_ref = None
+    for init, name in [(0, "newton_from_2"), (1, "newton_from_series"), (2, "newton_from_mlp")]:
+        s.set_f(f0)
+        P.lbm_set_elbm(s.h, init, 1e-10, 20)
+        P.lbm_elbm_stats(s.h, enable=True, reset=True)
+        ms = _time_steps(s, stream, torch, 100)
+        hist, nonconv = P.lbm_elbm_stats(s.h, enable=False)
+        u = s.macro()[1]
+        if u_ref is None:
+            u_ref = u
+        k = np.arange(len(hist))
+        elbm[name] = {"mlups": round(c4.n / ms / 1e3, 1),
+                      "mean_newton_iters": round(float((k * hist).sum() / max(hist.sum(), 1)), 4),
+                      "nonconverged": int(nonconv),
+                      "vel_rel_l2_vs_newton_from_2": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))}
+    s.close()
+    out["d3q19_elbm_taylor_green_256_fp32"] = elbm
+    print("[bench] ELBM done", file=sys.stderr, flush=True)
+
+    # D3Q19 two-component Shan-Chen 384^3, FP32: throughput and per-component conservation
+    c5 = S.c5_shan_chen(n=384)
+    s = P.Sim.from_case(c5, P.LBM_F32, P.LBM_AA, stream=stream)
+    d0 = s.diag()
+    ms = _time_steps(s, stream, torch, 100)
+    d1 = s.diag()
+    s.close()
+    out["d3q19_shan_chen_384_fp32"] = {"mlups": round(c5.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                                       "bytes_per_node": 472,
+                                       "hbm_gbs_algorithmic": round(472 * c5.n / (ms * 1e-3) / 1e9, 1),
+                                       "mass_rel_change": [float(abs(d1[c] - d0[c]) / d0[c]) for c in (0, 1)]}
+    print("[bench] Shan-Chen done", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +162,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="time the FP32 run only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the MRT duct, entropic/MLP and Shan-Chen rows")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -147,6 +245,8 @@ def main():
             variants[P.STORAGE_NAMES[st]] = v
             print("[bench] %s: %.1f MLUPS" % (P.STORAGE_NAMES[st], m2), file=sys.stderr, flush=True)
 
+    extras = {} if args.no_extras else run_extras(P, S, stream, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -183,6 +283,7 @@ def main():
                      "kernel": "k_step<D3Q19, F32, BGK>", "bytes_per_node": bpn,
                      "kernel_ms_per_launch": round(kern_ms, 5)},
         "variants": variants,
+        "extras": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

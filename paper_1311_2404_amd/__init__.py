@@ -24,6 +24,7 @@ LBM_AB, LBM_AA = 0, 1
 LBM_FLUID, LBM_WALL_BB = 0, 1
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSUPPORTED, LBM_EDIVERGED = 0, -1, -2, -3, -4, -5, -6
 MLP_NPARAM = 1313
+MLP_NTOTAL = 1325  # weights + input normalisation mu[6], isd[6]
 STORAGE_NAMES = {LBM_F64: "f64", LBM_F32: "f32", LBM_F32S: "f32s", LBM_BF16S: "bf16s", LBM_F16S: "f16s"}
 ELEM_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F32S: 4, LBM_BF16S: 2, LBM_F16S: 2}
 
@@ -200,8 +201,8 @@ def lbm_mlp_set_weights(sim, params):
     _err(sim, lib().lbm_mlp_set_weights(sim, p.ctypes.data_as(_fp), p.size))
 
 
-def lbm_mlp_get_weights(sim):
-    p = np.zeros(MLP_NPARAM, dtype=np.float32)
+def lbm_mlp_get_weights(sim, with_norm=True):
+    p = np.zeros(MLP_NTOTAL if with_norm else MLP_NPARAM, dtype=np.float32)
     _err(sim, lib().lbm_mlp_get_weights(sim, p.ctypes.data_as(_fp), p.size))
     return p
 

@@ -40,13 +40,14 @@ struct lbm_sim {
     double *red_d = nullptr;    // diag partials + result
     unsigned int *bad_d = nullptr;
     uint16_t *mlp_bf16 = nullptr;
-    float mlp_host[MLP_NPARAM] = {0};
+    float mlp_host[MLP_NTOTAL] = {0};  // FP32 weights + input normalisation (mu, isd)
     bool mlp_set = false;
     unsigned long long *stats_d = nullptr;
     bool stats_on = false;
     // MLP training state (FP32 master weights, Adam moments, scratch)
     float *mlp_w_d = nullptr, *mlp_m_d = nullptr, *mlp_v_d = nullptr, *mlp_g_d = nullptr;
-    float *mlp_norm_d = nullptr;  // mu[6], isd[6]
+    float *mlp_norm_d = nullptr;  // mu[6], isd[6] of the inference path (FP32)
+    float *mlp_tnorm_d = nullptr; // the same for a training pass
     float *mlp_part_d = nullptr;
     int64_t mlp_part_cap = 0;
     double *mlp_acc_d = nullptr;  // loss accumulator + feature moments scratch
@@ -129,6 +130,7 @@ StepParams base_params(const lbm_sim *s) {
     p.alpha_maxit = s->alpha_maxit;
     p.alpha_init = s->alpha_init;
     p.mlp = s->mlp_set ? s->mlp_bf16 : nullptr;
+    p.mlp_norm = s->mlp_norm_d;
     p.stats = s->stats_on ? s->stats_d : nullptr;
     p.psi = s->psi_d;
     p.G = s->G;
@@ -267,6 +269,7 @@ int lbm_create(int lattice, int model, int nx, int ny, int nz, double tau, const
     s->tau = tau;
     for (int a = 0; a < 3; a++) s->g[a] = g[a];
     for (int k = 0; k < 19; k++) s->s[k] = 1.0 / tau;
+    for (int k = 0; k < MLP_IN; k++) s->mlp_host[MLP_NPARAM + MLP_IN + k] = 1.0f;  // isd = 1
     if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
     *out = s;
     return LBM_OK;
@@ -517,7 +520,7 @@ void lbm_destroy(lbm_sim *s) {
     if (s->ready || s->flags_d) (void)hipStreamSynchronize(s->stream);
     void *ptrs[] = {s->buf[0], s->buf[1], s->flags_d, s->psi_d, s->stage, s->macro_d, s->red_d, s->bad_d,
                     s->mlp_bf16, s->stats_d, s->mlp_w_d, s->mlp_m_d, s->mlp_v_d, s->mlp_g_d,
-                    s->mlp_norm_d, s->mlp_part_d, s->mlp_acc_d};
+                    s->mlp_norm_d, s->mlp_tnorm_d, s->mlp_part_d, s->mlp_acc_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete s;
@@ -535,7 +538,8 @@ int mlp_alloc(lbm_sim *s, int64_t nbatch_max) {
         HIPCHK(s, hipMalloc(&s->mlp_m_d, sizeof(float) * MLP_NPARAM));
         HIPCHK(s, hipMalloc(&s->mlp_v_d, sizeof(float) * MLP_NPARAM));
         HIPCHK(s, hipMalloc(&s->mlp_g_d, sizeof(float) * MLP_NPARAM));
-        HIPCHK(s, hipMalloc(&s->mlp_norm_d, sizeof(float) * 12));
+        HIPCHK(s, hipMalloc(&s->mlp_norm_d, sizeof(float) * MLP_NNORM));
+        HIPCHK(s, hipMalloc(&s->mlp_tnorm_d, sizeof(float) * MLP_NNORM));
         HIPCHK(s, hipMalloc(&s->mlp_acc_d, sizeof(double) * (1 + 12 + 64 * 12)));
     }
     const int64_t parts = (nbatch_max + MLP_TRAIN_BLOCK - 1) / MLP_TRAIN_BLOCK;
@@ -550,6 +554,8 @@ int mlp_alloc(lbm_sim *s, int64_t nbatch_max) {
 
 int mlp_upload(lbm_sim *s) {
     HIPCHK(s, hipMemcpyAsync(s->mlp_w_d, s->mlp_host, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->mlp_norm_d, s->mlp_host + MLP_NPARAM, sizeof(float) * MLP_NNORM,
+                             hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, mlp_to_bf16(s->mlp_w_d, s->mlp_bf16, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return LBM_OK;
@@ -577,12 +583,18 @@ extern "C" {
 
 int lbm_mlp_set_weights(lbm_sim *s, const float *params, int n) {
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
-    if (!params || n != MLP_NPARAM) return fail(s, LBM_EINVAL, "params must hold 1313 values");
+    if (!params || (n != MLP_NPARAM && n != MLP_NTOTAL))
+        return fail(s, LBM_EINVAL, "params must hold 1313 (or 1325 with normalisation) values");
     for (int k = 0; k < n; k++)
         if (!std::isfinite(params[k])) return fail(s, LBM_EINVAL, "params must be finite");
     int rc = mlp_alloc(s, 1);
     if (rc) return rc;
-    std::memcpy(s->mlp_host, params, sizeof(float) * MLP_NPARAM);
+    std::memcpy(s->mlp_host, params, sizeof(float) * n);
+    if (n == MLP_NPARAM)
+        for (int k = 0; k < MLP_IN; k++) {
+            s->mlp_host[MLP_NPARAM + k] = 0.0f;
+            s->mlp_host[MLP_NPARAM + MLP_IN + k] = 1.0f;
+        }
     rc = mlp_upload(s);
     if (rc) return rc;
     s->mlp_set = true;
@@ -591,8 +603,9 @@ int lbm_mlp_set_weights(lbm_sim *s, const float *params, int n) {
 
 int lbm_mlp_get_weights(lbm_sim *s, float *params, int n) {
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
-    if (!params || n != MLP_NPARAM) return fail(s, LBM_EINVAL, "params must hold 1313 values");
-    std::memcpy(params, s->mlp_host, sizeof(float) * MLP_NPARAM);
+    if (!params || (n != MLP_NPARAM && n != MLP_NTOTAL))
+        return fail(s, LBM_EINVAL, "params must hold 1313 (or 1325 with normalisation) values");
+    std::memcpy(params, s->mlp_host, sizeof(float) * n);
     return LBM_OK;
 }
 
@@ -622,8 +635,8 @@ int lbm_mlp_forward(lbm_sim *s, const void *feat_dev, int64_t n, void *y_dev) {
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
     if (n < 0 || (n > 0 && (!feat_dev || !y_dev))) return fail(s, LBM_EINVAL, "bad count or NULL buffer");
     if (!s->mlp_set) return fail(s, LBM_ESTATE, "no MLP weights set");
-    HIPCHK(s, mlp_forward_bf16(s->mlp_bf16, static_cast<const float *>(feat_dev), n, static_cast<float *>(y_dev),
-                               s->stream));
+    HIPCHK(s, mlp_forward_bf16(s->mlp_bf16, s->mlp_norm_d, static_cast<const float *>(feat_dev), n,
+                               static_cast<float *>(y_dev), s->stream));
     return LBM_OK;
 }
 
@@ -633,13 +646,13 @@ int lbm_mlp_loss_grad(lbm_sim *s, const void *feat_dev, const void *alpha_dev, i
     if (!s->mlp_set) return fail(s, LBM_ESTATE, "no MLP weights set");
     int rc = mlp_alloc(s, n);
     if (rc) return rc;
-    const float norm[12] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
-    HIPCHK(s, hipMemcpyAsync(s->mlp_norm_d, norm, sizeof(norm), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->mlp_w_d, s->mlp_host, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->mlp_tnorm_d, s->mlp_host + MLP_NPARAM, sizeof(float) * MLP_NNORM,
+                             hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemsetAsync(s->mlp_acc_d, 0, sizeof(double), s->stream));
     HIPCHK(s, mlp_loss_grad(s->mlp_w_d, static_cast<const float *>(feat_dev), static_cast<const double *>(alpha_dev),
-                            n, s->mlp_norm_d, s->mlp_norm_d + 6, s->mlp_part_d, int(s->mlp_part_cap), s->mlp_g_d,
-                            s->mlp_acc_d, s->stream));
+                            n, s->mlp_tnorm_d, s->mlp_tnorm_d + MLP_IN, s->mlp_part_d, int(s->mlp_part_cap),
+                            s->mlp_g_d, s->mlp_acc_d, s->stream));
     HIPCHK(s, hipMemcpyAsync(grad, s->mlp_g_d, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipMemcpyAsync(loss, s->mlp_acc_d, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -651,6 +664,7 @@ int lbm_mlp_train(lbm_sim *s, const void *feat_dev, const void *alpha_dev, int64
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
     if (n <= 0 || !feat_dev || !alpha_dev || epochs < 0 || batch <= 0 || !(lr > 0.0f))
         return fail(s, LBM_EINVAL, "bad training arguments");
+    if (!s->mlp_set) return fail(s, LBM_ESTATE, "set initial weights with lbm_mlp_set_weights first");
     const int64_t bmax = std::min<int64_t>(batch, n);
     int rc = mlp_alloc(s, bmax);
     if (rc) return rc;
@@ -661,25 +675,28 @@ int lbm_mlp_train(lbm_sim *s, const void *feat_dev, const void *alpha_dev, int64
     double mom[12];
     HIPCHK(s, hipMemcpyAsync(mom, s->mlp_acc_d + 1, sizeof(mom), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    float mu[6], sd[6], norm[12];
-    for (int j = 0; j < 6; j++) {
+    // input normalisation fitted on the data: mu = mean, isd = 1/std
+    float norm[MLP_NNORM];
+    for (int j = 0; j < MLP_IN; j++) {
         const double m = mom[j] / double(n), var = mom[6 + j] / double(n) - m * m;
-        mu[j] = float(m);
-        sd[j] = var > 1e-24 ? float(std::sqrt(var)) : 1.0f;
-        norm[j] = mu[j];
-        norm[6 + j] = 1.0f / sd[j];
+        norm[j] = float(m);
+        norm[MLP_IN + j] = var > 1e-30 ? float(1.0 / std::sqrt(var)) : 1.0f;
     }
-    // express the current weights on normalised inputs: W1n = W1 diag(sd), b1n = b1 + W1 mu
-    float w[MLP_NPARAM];
+    // carry the current weights over to the new normalisation exactly:
+    // W1 diag(isd0) (x - mu0) + b1 = W1n diag(isd1) (x - mu1) + b1n
+    float w[MLP_NTOTAL];
     std::memcpy(w, s->mlp_host, sizeof(w));
     float *W1 = w, *b1 = w + MLP_H * MLP_IN;
+    const float *mu0 = s->mlp_host + MLP_NPARAM, *isd0 = mu0 + MLP_IN;
     for (int j = 0; j < MLP_H; j++)
         for (int k = 0; k < MLP_IN; k++) {
-            b1[j] += W1[j * MLP_IN + k] * mu[k];
-            W1[j * MLP_IN + k] *= sd[k];
+            const float a = W1[j * MLP_IN + k] * isd0[k];
+            b1[j] += a * (norm[k] - mu0[k]);
+            W1[j * MLP_IN + k] = a / norm[MLP_IN + k];
         }
-    HIPCHK(s, hipMemcpyAsync(s->mlp_norm_d, norm, sizeof(norm), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, hipMemcpyAsync(s->mlp_w_d, w, sizeof(w), hipMemcpyHostToDevice, s->stream));
+    std::memcpy(w + MLP_NPARAM, norm, sizeof(norm));
+    HIPCHK(s, hipMemcpyAsync(s->mlp_tnorm_d, norm, sizeof(norm), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->mlp_w_d, w, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemsetAsync(s->mlp_m_d, 0, sizeof(float) * MLP_NPARAM, s->stream));
     HIPCHK(s, hipMemsetAsync(s->mlp_v_d, 0, sizeof(float) * MLP_NPARAM, s->stream));
     int tstep = 0;
@@ -693,7 +710,7 @@ int lbm_mlp_train(lbm_sim *s, const void *feat_dev, const void *alpha_dev, int64
         int64_t nbatches = 0;
         for (int64_t r0 = 0; r0 < n; r0 += batch) {
             const int64_t nb = std::min<int64_t>(batch, n - r0);
-            HIPCHK(s, mlp_train_batch(s->mlp_w_d, x, t, r0, nb, n, pa, pb, s->mlp_norm_d, s->mlp_norm_d + 6,
+            HIPCHK(s, mlp_train_batch(s->mlp_w_d, x, t, r0, nb, n, pa, pb, s->mlp_tnorm_d, s->mlp_tnorm_d + MLP_IN,
                                       s->mlp_part_d, s->mlp_g_d, s->mlp_acc_d, s->stream));
             HIPCHK(s, mlp_adam(s->mlp_w_d, s->mlp_g_d, s->mlp_m_d, s->mlp_v_d, ++tstep, lr, s->stream));
             nbatches++;
@@ -705,14 +722,8 @@ int lbm_mlp_train(lbm_sim *s, const void *feat_dev, const void *alpha_dev, int64
             loss_out[e] = float(l / double(nbatches));
         }
     }
-    HIPCHK(s, hipMemcpyAsync(w, s->mlp_w_d, sizeof(w), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipMemcpyAsync(w, s->mlp_w_d, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
-    // fold the normalisation back: W1 = W1n diag(1/sd), b1 = b1n - W1 mu
-    for (int j = 0; j < MLP_H; j++)
-        for (int k = 0; k < MLP_IN; k++) {
-            W1[j * MLP_IN + k] /= sd[k];
-            b1[j] -= W1[j * MLP_IN + k] * mu[k];
-        }
     std::memcpy(s->mlp_host, w, sizeof(w));
     rc = mlp_upload(s);
     if (rc) return rc;

@@ -110,7 +110,8 @@ struct MlpDatasetParams {
     int layout;
 };
 hipError_t launch_alpha_dataset(int lattice, int storage, const MlpDatasetParams &p, hipStream_t s);
-hipError_t mlp_forward_bf16(const uint16_t *w, const float *x, int64_t n, float *y, hipStream_t s);
+hipError_t mlp_forward_bf16(const uint16_t *w, const float *norm, const float *x, int64_t n, float *y,
+                            hipStream_t s);
 hipError_t mlp_loss_grad(const float *w, const float *x, const double *t, int64_t n, const float *mu,
                          const float *isd, float *partials, int nparts, float *grad, double *loss, hipStream_t s);
 hipError_t mlp_train_batch(const float *w, const float *x, const double *t, int64_t row0, int64_t nbatch,

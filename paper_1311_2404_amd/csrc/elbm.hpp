@@ -57,8 +57,12 @@ __device__ __forceinline__ AlphaOut alpha_newton(const double *f, const double *
 
 // 6 -> 32 -> 32 -> 1 MLP, tanh hidden units, output 2 + linear; weights in LDS as
 // FP32 (converted from the BF16 copy), FP32 accumulation.  Layout: W1[32][6], b1[32],
-// W2[32][32], b2[32], w3[32], b3.
-__device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const float *x) {
+// W2[32][32], b2[32], w3[32], b3, then the FP32 input normalisation mu[6], isd[6]:
+// the network sees (x - mu) * isd.
+__device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const float *xraw) {
+    float x[MLP_IN];
+#pragma unroll
+    for (int k = 0; k < MLP_IN; k++) x[k] = (xraw[k] - W[MLP_NPARAM + k]) * W[MLP_NPARAM + MLP_IN + k];
     const float *W1 = W, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
     const float *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
     float h1[MLP_H];

@@ -75,9 +75,11 @@ __global__ __launch_bounds__(256) void k_alpha_dataset(MlpDatasetParams d) {
     d.valid[k] = ao.converged ? 1 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_forward_bf16(const uint16_t *wb, const float *x, int64_t n, float *y) {
-    __shared__ float s_w[MLP_NPARAM];
+__global__ __launch_bounds__(256) void k_mlp_forward_bf16(const uint16_t *wb, const float *norm, const float *x,
+                                                         int64_t n, float *y) {
+    __shared__ float s_w[MLP_NTOTAL];
     for (int k = threadIdx.x; k < MLP_NPARAM; k += blockDim.x) s_w[k] = __uint_as_float(uint32_t(wb[k]) << 16);
+    for (int k = threadIdx.x; k < MLP_NNORM; k += blockDim.x) s_w[MLP_NPARAM + k] = norm[k];
     __syncthreads();
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -256,9 +258,10 @@ hipError_t launch_alpha_dataset(int lattice, int storage, const MlpDatasetParams
     });
 }
 
-hipError_t mlp_forward_bf16(const uint16_t *w, const float *x, int64_t n, float *y, hipStream_t s) {
+hipError_t mlp_forward_bf16(const uint16_t *w, const float *norm, const float *x, int64_t n, float *y,
+                            hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_mlp_forward_bf16<<<dim3(uint32_t((n + 255) / 256)), 256, 0, s>>>(w, x, n, y);
+    k_mlp_forward_bf16<<<dim3(uint32_t((n + 255) / 256)), 256, 0, s>>>(w, norm, x, n, y);
     return hipGetLastError();
 }
 

@@ -10,6 +10,8 @@ enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3 };
 constexpr int MLP_IN = 6;
 constexpr int MLP_H = 32;
 constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 1313
+constexpr int MLP_NNORM = 2 * MLP_IN;                 // input normalisation mu[6], isd[6]
+constexpr int MLP_NTOTAL = MLP_NPARAM + MLP_NNORM;     // 1325
 constexpr int NEWTON_BINS = 32;
 
 // Passed by value as the kernel argument of every step-like kernel.
@@ -32,6 +34,7 @@ struct StepParams {
     int alpha_maxit;
     int alpha_init;             // 0: 2, 1: series, 2: MLP
     const uint16_t *mlp;        // bf16 MLP weights (alpha_init == 2)
+    const float *mlp_norm;      // FP32 input normalisation mu[6], isd[6]
     unsigned long long *stats;  // [NEWTON_BINS] histogram + [1] non-converged, or nullptr
     // Shan-Chen
     const void *psi;            // psi[2][N] in compute precision

@@ -112,11 +112,12 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     const int nthr = blockDim.x * blockDim.y;
 
     // ELBM only: MLP weights (FP32 from BF16) and the Newton-iteration histogram in LDS
-    __shared__ float s_mlp[MODEL == M_ELBM ? MLP_NPARAM : 1];
+    __shared__ float s_mlp[MODEL == M_ELBM ? MLP_NTOTAL : 1];
     __shared__ uint32_t s_hist[MODEL == M_ELBM ? NEWTON_BINS + 1 : 1];
     if constexpr (MODEL == M_ELBM) {
         if (p.alpha_init == 2 && p.mlp) {
             for (int k = tid; k < MLP_NPARAM; k += nthr) s_mlp[k] = __uint_as_float(uint32_t(p.mlp[k]) << 16);
+            for (int k = tid; k < MLP_NNORM; k += nthr) s_mlp[MLP_NPARAM + k] = p.mlp_norm[k];
         }
         if (p.stats)
             for (int k = tid; k < NEWTON_BINS + 1; k += nthr) s_hist[k] = 0u;
