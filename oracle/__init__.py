@@ -19,6 +19,7 @@ SRC = os.path.join(_HERE, "oracle.c")
 D2Q9, D3Q19 = 0, 1
 BGK, MRT, ELBM, SHANCHEN = 0, 1, 2, 3
 MLP_NPARAM = 1313
+MLP_NTOTAL = 1325  # weights + input normalisation mu[6], isd[6]
 
 
 def build(force: bool = False) -> str:
@@ -139,7 +140,16 @@ def alpha_features(lattice, f, fe, rho, vsq):
     return out
 
 
+def with_identity_norm(weights):
+    """1313 network weights -> 1325 parameters with mu = 0, isd = 1."""
+    return np.concatenate([_f64(weights)[:MLP_NPARAM], np.zeros(6), np.ones(6)])
+
+
 def mlp_forward(params, x):
+    """params: 1325 values (or 1313 weights, identity normalisation); x raw features."""
+    params = _f64(params)
+    if params.size == MLP_NPARAM:
+        params = with_identity_norm(params)
     x = _f64(x).reshape(-1, 6)
     y = np.zeros(x.shape[0])
     lib().orc_mlp_forward(_dp(_f64(params)), _dp(x), x.shape[0], _dp(y))
@@ -147,6 +157,9 @@ def mlp_forward(params, x):
 
 
 def mlp_loss_grad(params, x, t):
+    params = _f64(params)
+    if params.size == MLP_NPARAM:
+        params = with_identity_norm(params)
     x = _f64(x).reshape(-1, 6)
     t = _f64(t)
     g = np.zeros(MLP_NPARAM)

@@ -32,6 +32,7 @@
  */
 #include "oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -298,16 +299,18 @@ double orc_H(int lattice, const double *f) {
  * cancellation between the two H values (uses sum_i D_i ln(feq_i/w_i) = 0,
  * which holds because feq is the constrained minimiser and D carries no mass
  * or momentum). */
-static void g_dg(int q, const double *f, const double *D, double a, double *g, double *dg) {
-    double s = 0.0, ds = 0.0;
+static void g_dg(int q, const double *f, const double *D, double a, double *g, double *dg, double *gscale) {
+    double s = 0.0, ds = 0.0, sc = 0.0;
     for (int i = 0; i < q; i++) {
         double la = log1p(a * D[i] / f[i]);
         double l1 = log1p(D[i] / f[i]);
         s += (f[i] + a * D[i]) * la - a * D[i] * l1;
         ds += D[i] * (la - l1);
+        sc += fabs((f[i] + a * D[i]) * la) + fabs(a * D[i] * l1);
     }
     *g = s;
     *dg = ds;
+    *gscale = sc;
 }
 
 /* The six MLP inputs: log10(a2/rho), a3/a2, a4/a2, max(-d), max(d), |v|^2/c_s^2 with
@@ -338,14 +341,18 @@ void orc_alpha_features(int lattice, const double *f, const double *feq, double 
     alpha_features(q, f, D, rho, vsq, feat);
 }
 
-/* MLP 6 -> 32 -> 32 -> 1, tanh hidden layers, output 2 + linear.
- * Parameter layout: W1[32][6], b1[32], W2[32][32], b2[32], w3[32], b3. */
-static double mlp_eval(const double *p, const double *x, double *h1, double *h2) {
+/* MLP 6 -> 32 -> 32 -> 1, tanh hidden layers.  Parameters (1325): W1[32][6], b1[32],
+ * W2[32][32], b2[32], w3[32], b3, then the input normalisation mu[6], isd[6].  The
+ * network sees xn = (x - mu) * isd of the raw features x; its output is added to the
+ * series estimate of the root, 2 + (x[1] - 2 x[2]) / 3 = 2 + (a3 - 2 a4)/(3 a2), so the
+ * network only learns the series' residual. */
+static double mlp_eval(const double *p, const double *xraw, double *xn, double *h1, double *h2) {
     const double *W1 = p, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
-    const double *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
+    const double *w3 = b2 + MLP_H, *b3 = w3 + MLP_H, *mu = p + MLP_NPARAM, *isd = mu + MLP_IN;
+    for (int k = 0; k < MLP_IN; k++) xn[k] = (xraw[k] - mu[k]) * isd[k];
     for (int j = 0; j < MLP_H; j++) {
         double s = b1[j];
-        for (int k = 0; k < MLP_IN; k++) s += W1[j * MLP_IN + k] * x[k];
+        for (int k = 0; k < MLP_IN; k++) s += W1[j * MLP_IN + k] * xn[k];
         h1[j] = tanh(s);
     }
     for (int j = 0; j < MLP_H; j++) {
@@ -353,7 +360,7 @@ static double mlp_eval(const double *p, const double *x, double *h1, double *h2)
         for (int k = 0; k < MLP_H; k++) s += W2[j * MLP_H + k] * h1[k];
         h2[j] = tanh(s);
     }
-    double y = 2.0 + b3[0];
+    double y = 2.0 + (xraw[1] - 2.0 * xraw[2]) / 3.0 + b3[0];
     for (int k = 0; k < MLP_H; k++) y += w3[k] * h2[k];
     return y;
 }
@@ -361,21 +368,22 @@ static double mlp_eval(const double *p, const double *x, double *h1, double *h2)
 void orc_mlp_forward(const double *p, const double *x, int64_t n, double *y) {
 #pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < n; r++) {
-        double h1[MLP_H], h2[MLP_H];
-        y[r] = mlp_eval(p, x + MLP_IN * r, h1, h2);
+        double xn[MLP_IN], h1[MLP_H], h2[MLP_H];
+        y[r] = mlp_eval(p, x + MLP_IN * r, xn, h1, h2);
     }
 }
 
-/* Mean squared error (1/n) sum (y - t)^2 and its gradient by back-propagation. */
+/* Mean squared error (1/n) sum (y - t)^2 and its gradient with respect to the 1313
+ * network weights by back-propagation (the normalisation is held fixed). */
 double orc_mlp_loss_grad(const double *p, const double *x, const double *t, int64_t n, double *grad) {
     const double *W2 = p + MLP_H * MLP_IN + MLP_H;
     const double *w3 = W2 + MLP_H * MLP_H + MLP_H;
     double loss = 0.0;
     memset(grad, 0, sizeof(double) * MLP_NPARAM);
     for (int64_t r = 0; r < n; r++) {
-        double h1[MLP_H], h2[MLP_H], d2[MLP_H], d1[MLP_H];
+        double xn[MLP_IN], h1[MLP_H], h2[MLP_H], d2[MLP_H], d1[MLP_H];
         const double *xr = x + MLP_IN * r;
-        double y = mlp_eval(p, xr, h1, h2);
+        double y = mlp_eval(p, xr, xn, h1, h2);
         double err = y - t[r];
         loss += err * err;
         double dy = 2.0 * err / (double)n;
@@ -397,7 +405,7 @@ double orc_mlp_loss_grad(const double *p, const double *x, const double *t, int6
         }
         for (int j = 0; j < MLP_H; j++) {
             gb1[j] += d1[j];
-            for (int k = 0; k < MLP_IN; k++) gW1[j * MLP_IN + k] += d1[j] * xr[k];
+            for (int k = 0; k < MLP_IN; k++) gW1[j * MLP_IN + k] += d1[j] * xn[k];
         }
     }
     return loss / (double)n;
@@ -408,9 +416,12 @@ double orc_mlp_loss_grad(const double *p, const double *x, const double *t, int6
  * root is taken as 2, the value the paper gives for that limit.  Otherwise a
  * safeguarded Newton iteration: the bracket starts at [1, alpha_max) where
  * g(1) = H(feq) - H(f) <= 0 and alpha_max keeps every population positive;
- * stop when the Newton step |d alpha| <= tol, otherwise a Newton iterate
- * outside the bracket is replaced by the bracket's midpoint.  No convergence within
- * maxit: alpha = min(2, 0.99 alpha_max).  f = populations, D = feq - f. */
+ * stop when the Newton step |d alpha| <= tol, or when g itself is below 64 ulps of the
+ * sum of the magnitudes of its terms (just above the short-cut, g' ~ sum f d^2 is so
+ * small that the rounding noise of g alone moves a Newton step by more than tol);
+ * otherwise a Newton iterate outside the bracket is replaced by the bracket's midpoint.
+ * No convergence within maxit: alpha = min(2, 0.99 alpha_max).  f = populations,
+ * D = feq - f. */
 static double alpha_solve(int q, const double *f, const double *D, int init, const double *mlp, double rho,
                           double vsq, double tol, int maxit, int *iters, int *converged) {
     double dmax = 0.0, amax = INFINITY;
@@ -434,19 +445,17 @@ static double alpha_solve(int q, const double *f, const double *D, int init, con
         }
         a0 = 2.0 + (a3 - 2.0 * a4) / (3.0 * a2);
     } else if (init == 2 && mlp) {
-        /* mlp = 1313 network weights followed by the input normalisation mu[6], isd[6]:
-         * the network sees (x - mu) * isd */
-        double feat[MLP_IN], h1[MLP_H], h2[MLP_H];
+        double feat[MLP_IN], xn[MLP_IN], h1[MLP_H], h2[MLP_H];
         alpha_features(q, f, D, rho, vsq, feat);
-        for (int k = 0; k < MLP_IN; k++) feat[k] = (feat[k] - mlp[MLP_NPARAM + k]) * mlp[MLP_NPARAM + MLP_IN + k];
-        a0 = mlp_eval(mlp, feat, h1, h2);
+        a0 = mlp_eval(mlp, feat, xn, h1, h2);
     }
     double lo = 1.0, hi = amax, a = a0;
     if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
     for (int k = 1; k <= maxit; k++) {
-        double g, dg;
-        g_dg(q, f, D, a, &g, &dg);
-        if (g == 0.0) {
+        double g, dg, gs;
+        g_dg(q, f, D, a, &g, &dg, &gs);
+        /* g at the rounding floor of its own sum: a is the root to working precision */
+        if (fabs(g) <= 64.0 * DBL_EPSILON * gs) {
             *iters = k;
             return a;
         }

@@ -40,7 +40,7 @@ typedef struct {
     int alpha_init;       /* ELBM first guess: 0 -> 2, 1 -> series, 2 -> MLP */
     double alpha_tol;     /* Newton stop |d alpha| <= tol */
     int alpha_maxit;
-    const double *mlp;    /* alpha_init == 2: 1313 MLP weights, then mu[6], isd[6] (inputs (x-mu)*isd) */
+    const double *mlp;    /* alpha_init == 2: 1325 MLP parameters (1313 weights, mu[6], isd[6]) */
     double G;             /* Shan-Chen coupling */
     int psi;              /* 0: psi = rho, 1: psi = 1 - exp(-rho) */
 } orc_params;
@@ -61,6 +61,7 @@ double orc_alpha(int lattice, const double *f, const double *feq, int init, cons
                  double vsq, double tol, int maxit, int *iters, int *converged);
 void orc_alpha_features(int lattice, const double *f, const double *feq, double rho, double vsq,
                         double *feat /* 6 */);
+/* MLP on raw features x[n][6] with parameters p[1325]; gradient over the first 1313 */
 void orc_mlp_forward(const double *p, const double *x, int64_t n, double *y);
 double orc_mlp_loss_grad(const double *p, const double *x, const double *t, int64_t n, double *grad);
 void orc_collide_node(const orc_params *P, const double *f, double *out);

@@ -569,19 +569,35 @@ def test_mlp_gradient_matches_central_differences():
 
 
 def test_mlp_forward_special_cases():
-    p = np.zeros(oracle.MLP_NPARAM)
-    p[-1] = 0.25
+    """Zero network: the proposal is the series estimate 2 + (a3 - 2 a4)/(3 a2) (from
+    features 1 and 2) plus the output bias; one hidden path adds w3 tanh(...)."""
     x = np.random.default_rng(1).standard_normal((5, 6))
-    np.testing.assert_array_equal(oracle.mlp_forward(p, x), np.full(5, 2.25))
-    # one hidden path: y = 2 + w3_0 tanh(b2_0 + W2_00 tanh(W1_00 x0))
+    series = 2 + (x[:, 1] - 2 * x[:, 2]) / 3
+    p = np.zeros(oracle.MLP_NPARAM)
+    p[oracle.MLP_NPARAM - 1] = 0.25
+    np.testing.assert_allclose(oracle.mlp_forward(p, x), series + 0.25, rtol=1e-15)
     p = np.zeros(oracle.MLP_NPARAM)
     p[0] = 0.7               # W1[0][0]
     o_w2 = 32 * 6 + 32
     p[o_w2] = 1.3            # W2[0][0]
     p[o_w2 + 1024] = -0.2    # b2[0]
     p[o_w2 + 1024 + 32] = 0.5  # w3[0]
-    y = oracle.mlp_forward(p, x)
-    np.testing.assert_allclose(y, 2 + 0.5 * np.tanh(-0.2 + 1.3 * np.tanh(0.7 * x[:, 0])), rtol=1e-15)
+    mu, isd = np.full(6, 0.3), np.full(6, 2.0)
+    y = oracle.mlp_forward(np.concatenate([p, mu, isd]), x)
+    xn0 = (x[:, 0] - 0.3) * 2.0
+    np.testing.assert_allclose(y, series + 0.5 * np.tanh(-0.2 + 1.3 * np.tanh(0.7 * xn0)), rtol=1e-15)
+
+
+def test_mlp_series_base_is_the_newton_series():
+    """With a zero network, the MLP-initialised alpha solve starts at the series estimate;
+    its features give the same start as init = 1."""
+    rng = np.random.default_rng(21)
+    zero = oracle.with_identity_norm(np.zeros(oracle.MLP_NPARAM))
+    for _ in range(10):
+        f, fe, rho, u = _near_eq(S.D3Q19, rng, 1e-3)
+        a_ser = oracle.alpha(S.D3Q19, f, fe, init=1, maxit=1)
+        a_mlp = oracle.alpha(S.D3Q19, f, fe, init=2, mlp=zero, vsq=float(u @ u), maxit=1)
+        assert abs(a_ser[0] - a_mlp[0]) <= 1e-12
 
 
 def test_init_is_equilibrium_plus_perturbation():
