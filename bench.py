@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the MRT duct, entropic/MLP and Shan-Chen rows")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run 3 plain device copies of MIB MiB (calibrates HBM byte counters in profiles)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -206,6 +208,14 @@ def main():
         kern_ms = e0.elapsed_time(e1) / steps
         s.close()
         return wall, kern_ms
+
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe * 2 ** 20 // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # headline: FP32 storage
     wall, kern_ms = timed(P.LBM_F32, args.steps, args.warmup)

@@ -91,9 +91,12 @@ size_t compute_size(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 LaunchCfg node_cfg(const lbm_sim *s) {
     int bx, by;
+#ifndef LBM_BLOCK_NODES
+#define LBM_BLOCK_NODES 256  // nodes per workgroup when whole rows fit (build-time tuning)
+#endif
     if (s->nx % 64 == 0 && s->nx <= 512) {
         bx = s->nx;
-        by = std::max(1, 256 / s->nx);
+        by = std::max(1, LBM_BLOCK_NODES / s->nx);
     } else {
         bx = std::min(256, ((s->nx + 63) / 64) * 64);
         by = std::max(1, 256 / bx);
@@ -540,7 +543,7 @@ int mlp_alloc(lbm_sim *s, int64_t nbatch_max) {
         HIPCHK(s, hipMalloc(&s->mlp_g_d, sizeof(float) * MLP_NPARAM));
         HIPCHK(s, hipMalloc(&s->mlp_norm_d, sizeof(float) * MLP_NNORM));
         HIPCHK(s, hipMalloc(&s->mlp_tnorm_d, sizeof(float) * MLP_NNORM));
-        HIPCHK(s, hipMalloc(&s->mlp_acc_d, sizeof(double) * (1 + 12 + 64 * 12)));
+        HIPCHK(s, hipMalloc(&s->mlp_acc_d, sizeof(double) * (1 + 12 + 64 * 12 + 2 + 2 * 64)));
     }
     const int64_t parts = (nbatch_max + MLP_TRAIN_BLOCK - 1) / MLP_TRAIN_BLOCK;
     if (parts > s->mlp_part_cap) {
@@ -695,6 +698,19 @@ int lbm_mlp_train(lbm_sim *s, const void *feat_dev, const void *alpha_dev, int64
             W1[j * MLP_IN + k] = a / norm[MLP_IN + k];
         }
     std::memcpy(w + MLP_NPARAM, norm, sizeof(norm));
+    // the target is the series residual, standardised: r = (alpha - base - tmean) / tsd;
+    // the output layer (w3, b3) is carried into those units and back exactly at the end
+    double *racc = s->mlp_acc_d + 1 + 12 + 64 * 12;
+    HIPCHK(s, mlp_resid_moments(x, t, n, racc, s->stream));
+    double rm[2];
+    HIPCHK(s, hipMemcpyAsync(rm, racc, sizeof(rm), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    const double tmean = rm[0] / double(n);
+    const double tvar = rm[1] / double(n) - tmean * tmean;
+    const double tsd = tvar > 1e-40 ? std::sqrt(tvar) : 1.0;
+    float *w3 = w + MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H, *b3 = w3 + MLP_H;
+    for (int j = 0; j < MLP_H; j++) w3[j] = float(w3[j] / tsd);
+    b3[0] = float((b3[0] - tmean) / tsd);
     HIPCHK(s, hipMemcpyAsync(s->mlp_tnorm_d, norm, sizeof(norm), hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->mlp_w_d, w, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemsetAsync(s->mlp_m_d, 0, sizeof(float) * MLP_NPARAM, s->stream));
@@ -711,7 +727,7 @@ int lbm_mlp_train(lbm_sim *s, const void *feat_dev, const void *alpha_dev, int64
         for (int64_t r0 = 0; r0 < n; r0 += batch) {
             const int64_t nb = std::min<int64_t>(batch, n - r0);
             HIPCHK(s, mlp_train_batch(s->mlp_w_d, x, t, r0, nb, n, pa, pb, s->mlp_tnorm_d, s->mlp_tnorm_d + MLP_IN,
-                                      s->mlp_part_d, s->mlp_g_d, s->mlp_acc_d, s->stream));
+                                      tmean, 1.0 / tsd, s->mlp_part_d, s->mlp_g_d, s->mlp_acc_d, s->stream));
             HIPCHK(s, mlp_adam(s->mlp_w_d, s->mlp_g_d, s->mlp_m_d, s->mlp_v_d, ++tstep, lr, s->stream));
             nbatches++;
         }
@@ -719,11 +735,13 @@ int lbm_mlp_train(lbm_sim *s, const void *feat_dev, const void *alpha_dev, int64
             double l = 0.0;
             HIPCHK(s, hipMemcpyAsync(&l, s->mlp_acc_d, sizeof(double), hipMemcpyDeviceToHost, s->stream));
             HIPCHK(s, hipStreamSynchronize(s->stream));
-            loss_out[e] = float(l / double(nbatches));
+            loss_out[e] = float(l / double(nbatches) * tsd * tsd);  // in alpha units
         }
     }
     HIPCHK(s, hipMemcpyAsync(w, s->mlp_w_d, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int j = 0; j < MLP_H; j++) w3[j] = float(w3[j] * tsd);
+    b3[0] = float(b3[0] * tsd + tmean);
     std::memcpy(s->mlp_host, w, sizeof(w));
     rc = mlp_upload(s);
     if (rc) return rc;

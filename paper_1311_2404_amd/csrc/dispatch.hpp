@@ -115,8 +115,10 @@ hipError_t mlp_forward_bf16(const uint16_t *w, const float *norm, const float *x
 hipError_t mlp_loss_grad(const float *w, const float *x, const double *t, int64_t n, const float *mu,
                          const float *isd, float *partials, int nparts, float *grad, double *loss, hipStream_t s);
 hipError_t mlp_train_batch(const float *w, const float *x, const double *t, int64_t row0, int64_t nbatch,
-                           int64_t n_all, uint64_t pa, uint64_t pb, const float *mu, const float *isd,
-                           float *partials, float *grad, double *loss_acc, hipStream_t s);
+                           int64_t n_all, uint64_t pa, uint64_t pb, const float *mu, const float *isd, double tmean,
+                           double tinv, float *partials, float *grad, double *loss_acc, hipStream_t s);
+// acc[0] = sum, acc[1] = sum of squares of alpha - series base; acc[2 .. 2 + 128) scratch
+hipError_t mlp_resid_moments(const float *x, const double *t, int64_t n, double *acc, hipStream_t s);
 constexpr int MLP_TRAIN_BLOCK = 256;
 hipError_t mlp_adam(float *w, const float *grad, float *m, float *v, int t, float lr, hipStream_t s);
 hipError_t mlp_to_bf16(const float *w, uint16_t *wb, hipStream_t s);

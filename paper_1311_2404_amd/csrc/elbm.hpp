@@ -9,8 +9,10 @@
 // and g(1) = H(feq) - H(f) <= 0, so the root lies in (1, a_max), a_max the largest
 // step keeping every population positive.  The paper notes alpha = 2 close to
 // equilibrium: nodes with max |d_i| < 1e-6 take alpha = 2 directly.  Otherwise
-// Newton with bisection safeguard on the bracket [lo, hi]; all in FP64 with
-// denormals kept (the paper reports flush-to-zero breaking ELBM).
+// Newton with bisection safeguard on the bracket [lo, hi], stopped by |d alpha| <= tol
+// or by g reaching the rounding floor of its own terms (just above the short-cut,
+// g' ~ sum f d^2 is tiny and rounding noise alone moves a Newton step by more than
+// tol); all in FP64 with denormals kept (the paper reports flush-to-zero breaking ELBM).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -37,15 +39,18 @@ __device__ __forceinline__ AlphaOut alpha_newton(const double *f, const double *
     double lo = 1.0, hi = amax, a = a0;
     if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
     for (int k = 1; k <= maxit; k++) {
-        double g = 0.0, dg = 0.0;
+        double g = 0.0, dg = 0.0, gs = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             const double ad = a * d[i];
             const double la = log1p(ad);
-            g += f[i] * ((1.0 + ad) * la - ad * l1[i]);
+            const double t1 = f[i] * (1.0 + ad) * la, t2 = f[i] * ad * l1[i];
+            g += t1 - t2;
             dg += f[i] * d[i] * (la - l1[i]);
+            gs += fabs(t1) + fabs(t2);
         }
-        if (g == 0.0) return {a, k, 1};
+        // g at the rounding floor of its own sum: a is the root to working precision
+        if (fabs(g) <= 64.0 * 2.220446049250313e-16 * gs) return {a, k, 1};
         if (g < 0.0) lo = a; else hi = a;
         double an = a - g / dg;
         if (fabs(an - a) <= tol) return {an, k, 1};
@@ -55,10 +60,12 @@ __device__ __forceinline__ AlphaOut alpha_newton(const double *f, const double *
     return {fmin(2.0, 0.99 * amax), maxit, 0};
 }
 
-// 6 -> 32 -> 32 -> 1 MLP, tanh hidden units, output 2 + linear; weights in LDS as
-// FP32 (converted from the BF16 copy), FP32 accumulation.  Layout: W1[32][6], b1[32],
-// W2[32][32], b2[32], w3[32], b3, then the FP32 input normalisation mu[6], isd[6]:
-// the network sees (x - mu) * isd.
+// 6 -> 32 -> 32 -> 1 MLP, tanh hidden units; weights in LDS as FP32 (converted from
+// the BF16 copy), FP32 accumulation.  Layout: W1[32][6], b1[32], W2[32][32], b2[32],
+// w3[32], b3, then the FP32 input normalisation mu[6], isd[6]: the network sees
+// (x - mu) * isd.  Its output is added to the series estimate of the root,
+// 2 + (x1 - 2 x2)/3 = 2 + (a3 - 2 a4)/(3 a2), so it only carries the series' residual
+// (which BF16 weights can represent to far better absolute accuracy than alpha - 2).
 __device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const float *xraw) {
     float x[MLP_IN];
 #pragma unroll
@@ -73,7 +80,7 @@ __device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const
         for (int k = 0; k < MLP_IN; k++) s = fmaf(W1[j * MLP_IN + k], x[k], s);
         h1[j] = tanhf(s);
     }
-    float y = 2.0f + b3[0];
+    float y = b3[0];
 #pragma unroll 4
     for (int j = 0; j < MLP_H; j++) {
         float s = b2[j];
@@ -81,7 +88,7 @@ __device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const
         for (int k = 0; k < MLP_H; k++) s = fmaf(W2[j * MLP_H + k], h1[k], s);
         y = fmaf(w3[j], tanhf(s), y);
     }
-    return y;
+    return (2.0f + (xraw[1] - 2.0f * xraw[2]) * (1.0f / 3.0f)) + y;
 }
 
 // The six alpha features: log10(a2/rho), a3/a2, a4/a2, max(-d), max(d), |v|^2/c_s^2,

@@ -1,7 +1,10 @@
 // The ELBM alpha proposal MLP: training data sampler, inference and training kernels.
 //
-// The network (6 -> 32 -> 32 -> 1, tanh hidden units, output 2 + linear) proposes the
-// first Newton iterate of the entropic alpha; Newton remains the judge of the result.
+// The network (6 -> 32 -> 32 -> 1, tanh hidden units) adds its output to the series
+// estimate 2 + (a3 - 2 a4)/(3 a2) of the entropic alpha to propose the first Newton
+// iterate; Newton remains the judge of the result.  Training minimises the squared
+// error of the proposal, i.e. of the network against the series residual alpha - base,
+// which is formed in FP64 so that the small residual is not lost to FP32 rounding.
 // Training is plain minibatch MSE with Adam in FP32; gradients are reduced across a
 // wave with lane shuffles, then across the waves of a block and across blocks in a
 // fixed order, so a training run is deterministic.
@@ -104,8 +107,8 @@ constexpr int TW = TB / 64;        // waves per block
 // squared-error sum into partials[block][MLP_NPARAM + 1].
 __global__ __launch_bounds__(TB) void k_mlp_grad(const float *w, const float *xall, const double *tall,
                                                  int64_t row0, int64_t nbatch, int64_t n_all, uint64_t pa,
-                                                 uint64_t pb, const float *mu, const float *isd,
-                                                 float *partials) {
+                                                 uint64_t pb, const float *mu, const float *isd, double tmean,
+                                                 double tinv, float *partials) {
     __shared__ float s_w[MLP_NPARAM];
     __shared__ float s_g[TW][MLP_NPARAM + 1];
     for (int k = threadIdx.x; k < MLP_NPARAM; k += TB) s_w[k] = w[k];
@@ -114,12 +117,15 @@ __global__ __launch_bounds__(TB) void k_mlp_grad(const float *w, const float *xa
     const int64_t r = int64_t(blockIdx.x) * TB + threadIdx.x;
     const bool live = r < nbatch;
     float x[MLP_IN] = {0, 0, 0, 0, 0, 0};
-    float t = 2.0f;
+    float base = 2.0f, t = 2.0f;
     if (live) {
         const int64_t gr = row0 + r;
         const int64_t row = pa ? int64_t((pa * uint64_t(gr) + pb) % uint64_t(n_all)) : gr;
-        for (int j = 0; j < MLP_IN; j++) x[j] = (xall[MLP_IN * row + j] - mu[j]) * isd[j];
-        t = float(tall[row]);
+        const float *xr = xall + MLP_IN * row;
+        for (int j = 0; j < MLP_IN; j++) x[j] = (xr[j] - mu[j]) * isd[j];
+        base = 2.0f + (xr[1] - 2.0f * xr[2]) * (1.0f / 3.0f);  // series estimate
+        // the target: the series residual, standardised, formed in FP64 before rounding
+        t = float((tall[row] - double(base) - tmean) * tinv);
     }
     const float *W1 = s_w, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
     const float *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
@@ -131,7 +137,7 @@ __global__ __launch_bounds__(TB) void k_mlp_grad(const float *w, const float *xa
         for (int k = 0; k < MLP_IN; k++) s = fmaf(W1[j * MLP_IN + k], x[k], s);
         h1[j] = tanhf(s);
     }
-    float yv = 2.0f + b3[0];
+    float yv = b3[0];  // network output; the proposal is base + yv
 #pragma unroll 4
     for (int j = 0; j < MLP_H; j++) {
         float s = b2[j];
@@ -216,6 +222,37 @@ __global__ void k_to_bf16(const float *w, uint16_t *wb) {
     wb[k] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(w[k]));
 }
 
+// sums and sums of squares of the series residual alpha - (2 + (x1 - 2 x2)/3)
+__global__ __launch_bounds__(256) void k_resid_moments(const float *x, const double *t, int64_t n, double *partials) {
+    __shared__ double s[2][256];
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n; r += int64_t(gridDim.x) * 256) {
+        const float base = 2.0f + (x[6 * r + 1] - 2.0f * x[6 * r + 2]) * (1.0f / 3.0f);
+        const double v = t[r] - double(base);
+        a0 += v;
+        a1 += v * v;
+    }
+    s[0][threadIdx.x] = a0;
+    s[1][threadIdx.x] = a1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + w];
+            s[1][threadIdx.x] += s[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) partials[blockIdx.x * 2 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_resid_final(const double *partials, int nb, double *out) {
+    const int j = threadIdx.x;
+    if (j >= 2) return;
+    double a = 0.0;
+    for (int b = 0; b < nb; b++) a += partials[b * 2 + j];
+    out[j] = a;
+}
+
 // sums and sums of squares of the 6 features (FP64, fixed-order two-level reduction)
 __global__ __launch_bounds__(256) void k_moments(const float *x, int64_t n, double *partials) {
     __shared__ double s[12][256];
@@ -270,7 +307,7 @@ hipError_t mlp_loss_grad(const float *w, const float *x, const double *t, int64_
                          const float *isd, float *partials, int nparts, float *grad, double *loss, hipStream_t s) {
     if (n <= 0 || nparts < int((n + TB - 1) / TB)) return hipErrorInvalidValue;
     const int nb = int((n + TB - 1) / TB);
-    k_mlp_grad<<<nb, TB, 0, s>>>(w, x, t, 0, n, n, 0, 0, mu, isd, partials);
+    k_mlp_grad<<<nb, TB, 0, s>>>(w, x, t, 0, n, n, 0, 0, mu, isd, 0.0, 1.0, partials);
     k_mlp_reduce<<<(MLP_NPARAM + 1 + 255) / 256, 256, 0, s>>>(partials, nb, grad, loss, n);
     return hipGetLastError();
 }
@@ -286,6 +323,13 @@ hipError_t mlp_to_bf16(const float *w, uint16_t *wb, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t mlp_resid_moments(const float *x, const double *t, int64_t n, double *acc, hipStream_t s) {
+    const int nb = 64;
+    k_resid_moments<<<nb, 256, 0, s>>>(x, t, n, acc + 2);
+    k_resid_final<<<1, 64, 0, s>>>(acc + 2, nb, acc);
+    return hipGetLastError();
+}
+
 hipError_t mlp_moments(const float *x, int64_t n, double *acc, hipStream_t s) {
     const int nb = 64;
     k_moments<<<nb, 256, 0, s>>>(x, n, acc + 12);
@@ -295,10 +339,10 @@ hipError_t mlp_moments(const float *x, int64_t n, double *acc, hipStream_t s) {
 
 // One training minibatch: rows row0 .. row0 + nbatch - 1 of the permuted order.
 hipError_t mlp_train_batch(const float *w, const float *x, const double *t, int64_t row0, int64_t nbatch,
-                           int64_t n_all, uint64_t pa, uint64_t pb, const float *mu, const float *isd,
-                           float *partials, float *grad, double *loss_acc, hipStream_t s) {
+                           int64_t n_all, uint64_t pa, uint64_t pb, const float *mu, const float *isd, double tmean,
+                           double tinv, float *partials, float *grad, double *loss_acc, hipStream_t s) {
     const int nb = int((nbatch + TB - 1) / TB);
-    k_mlp_grad<<<nb, TB, 0, s>>>(w, x, t, row0, nbatch, n_all, pa, pb, mu, isd, partials);
+    k_mlp_grad<<<nb, TB, 0, s>>>(w, x, t, row0, nbatch, n_all, pa, pb, mu, isd, tmean, tinv, partials);
     k_mlp_reduce<<<(MLP_NPARAM + 1 + 255) / 256, 256, 0, s>>>(partials, nb, grad, loss_acc, nbatch);
     return hipGetLastError();
 }

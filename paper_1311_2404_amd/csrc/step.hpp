@@ -105,9 +105,26 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     using T = typename St::T;
     using C = typename St::C;
     constexpr int Q = L::Q;
+#if defined(LBM_XCD_REMAP)
+    // build variant: workgroups are dealt to the 8 XCDs round-robin by linear id; remap
+    // so that each XCD walks one contiguous slab of rows
+    uint32_t by = blockIdx.y, bz = blockIdx.z;
+    {
+        const uint32_t T8 = gridDim.y * gridDim.z, lin = blockIdx.y + gridDim.y * blockIdx.z;
+        if (gridDim.x == 1 && T8 % 8 == 0) {
+            const uint32_t r = (lin % 8) * (T8 / 8) + lin / 8;
+            by = r % gridDim.y;
+            bz = r / gridDim.y;
+        }
+    }
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = by * blockDim.y + threadIdx.y;
+    const int z = bz;
+#else
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
+#endif
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const int nthr = blockDim.x * blockDim.y;
 
