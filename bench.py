@@ -108,10 +108,7 @@ def run_extras(P, S, stream, torch):
     feat = torch.cat(feats).contiguous()
     alpha = torch.cat(alphas).contiguous()
     torch.cuda.synchronize()  # produced on torch's stream, consumed on the library's
-    rng = np.random.default_rng(20131124)
-    p0 = (0.1 * rng.standard_normal(P.MLP_NPARAM)).astype(np.float32)
-    p0[-1] = 0.0
-    P.lbm_mlp_set_weights(s.h, p0)
+    P.lbm_mlp_set_weights(s.h, P.mlp_initial_weights(20131124))
     t0 = time.perf_counter()
     loss = P.lbm_mlp_train(s.h, feat, alpha, len(alpha), 20, 4096, 1e-3, 7) if len(alpha) else []
     t_train = time.perf_counter() - t0
@@ -137,17 +134,20 @@ def run_extras(P, S, stream, torch):
     out["d3q19_elbm_taylor_green_256_fp32"] = elbm
     print("[bench] ELBM done", file=sys.stderr, flush=True)
 
-    # D3Q19 two-component Shan-Chen 384^3, FP32: throughput and per-component conservation
+    # D3Q19 two-component Shan-Chen 384^3, FP32 compute: throughput and per-component
+    # conservation, with plain and with shifted FP32 storage (same bytes per node)
     c5 = S.c5_shan_chen(n=384)
-    s = P.Sim.from_case(c5, P.LBM_F32, P.LBM_AA, stream=stream)
-    d0 = s.diag()
-    ms = _time_steps(s, stream, torch, 100)
-    d1 = s.diag()
-    s.close()
-    out["d3q19_shan_chen_384_fp32"] = {"mlups": round(c5.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
-                                       "bytes_per_node": 472,
-                                       "hbm_gbs_algorithmic": round(472 * c5.n / (ms * 1e-3) / 1e9, 1),
-                                       "mass_rel_change": [float(abs(d1[c] - d0[c]) / d0[c]) for c in (0, 1)]}
+    for st, tag in [(P.LBM_F32, "fp32"), (P.LBM_F32S, "f32s")]:
+        s = P.Sim.from_case(c5, st, P.LBM_AA, stream=stream)
+        d0 = s.diag()
+        ms = _time_steps(s, stream, torch, 100)
+        d1 = s.diag()
+        s.close()
+        out["d3q19_shan_chen_384_" + tag] = {"mlups": round(c5.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                                             "bytes_per_node": 472,
+                                             "hbm_gbs_algorithmic": round(472 * c5.n / (ms * 1e-3) / 1e9, 1),
+                                             "steps": 100,
+                                             "mass_rel_change": [float(abs(d1[c] - d0[c]) / d0[c]) for c in (0, 1)]}
     print("[bench] Shan-Chen done", file=sys.stderr, flush=True)
     return out
 
@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the MRT duct, entropic/MLP and Shan-Chen rows")
+    ap.add_argument("--no-errors", action="store_true",
+                    help="skip the 1000-step velocity-error runs (for short profiled runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run 3 plain device copies of MIB MiB (calibrates HBM byte counters in profiles)")
     args = ap.parse_args()
@@ -233,16 +235,19 @@ def main():
         s.close()
         return u
 
-    u64 = run_fields(P.LBM_F64)
+    u64 = None if args.no_errors else run_fields(P.LBM_F64)
     k = 2 * np.pi / n
     ke_law = float(np.exp(-6 * case.extra["nu"] * k * k * ERR_STEPS))
     ke0 = float((case.u ** 2).sum())
 
-    def errs(u):
+    def errs(storage):
+        if u64 is None:
+            return {}
+        u = run_fields(storage)
         return {"vel_rel_l2_vs_fp64": float(np.linalg.norm(u - u64) / np.linalg.norm(u64)),
                 "ke_ratio": float((u ** 2).sum() / ke0), "ke_ratio_ns_law": ke_law}
 
-    variants = {"f32": dict(mlups=round(mlups, 1), bytes_per_node=bpn, **errs(run_fields(P.LBM_F32)))}
+    variants = {"f32": dict(mlups=round(mlups, 1), bytes_per_node=bpn, **errs(P.LBM_F32))}
     if not args.no_variants:
         for st in (P.LBM_F32S, P.LBM_BF16S, P.LBM_F16S, P.LBM_F64):
             w2, k2 = timed(st, args.steps, args.warmup)
@@ -251,7 +256,7 @@ def main():
             v = dict(mlups=round(m2, 1), bytes_per_node=b2,
                      hbm_gbs_algorithmic=round(b2 * N / (k2 * 1e-3) / 1e9, 1))
             if st != P.LBM_F64:
-                v.update(errs(run_fields(st)))
+                v.update(errs(st))
             variants[P.STORAGE_NAMES[st]] = v
             print("[bench] %s: %.1f MLUPS" % (P.STORAGE_NAMES[st], m2), file=sys.stderr, flush=True)
 

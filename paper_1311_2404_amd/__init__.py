@@ -207,6 +207,19 @@ def lbm_mlp_get_weights(sim, with_norm=True):
     return p
 
 
+def mlp_initial_weights(seed):
+    """Starting weights for training a new proposal network (1313 values, the layout of
+    lbm_mlp_set_weights): Glorot-scaled normal hidden layers, zero biases and a zero
+    output layer.  The proposal then starts as the bare series estimate, and training
+    (in standardised target units) grows the output layer from zero instead of having
+    to cancel a large random one, which BF16 inference weights could not represent."""
+    rng = np.random.default_rng(seed)
+    h, nin = 32, 6
+    w1 = rng.standard_normal((h, nin)) * np.sqrt(2.0 / (h + nin))
+    w2 = rng.standard_normal((h, h)) * np.sqrt(1.0 / h)
+    return np.concatenate([w1.ravel(), np.zeros(h), w2.ravel(), np.zeros(h), np.zeros(h), [0.0]]).astype(np.float32)
+
+
 def lbm_alpha_dataset(sim, n, seed, feat_t, alpha_t, valid_t):
     import torch
     _err(sim, lib().lbm_alpha_dataset(sim, int(n), int(seed), _ptr(feat_t, 6 * n, torch.float32),

@@ -30,6 +30,27 @@ struct AlphaOut {
 
 constexpr double ALPHA_SHORTCUT = 1e-6;
 
+// Remove from D the mass and momentum it carries through rounding.  The form of g above
+// relies on sum_i D_i = 0 and sum_i e_i D_i = 0; with D from an FP32 equilibrium those
+// sums are ~1e-9, which near equilibrium outweighs g's own scale sum_i f_i d_i^2 / 2 and
+// moves the root below 1, out of the bracket.  Subtracting w_i (dm + 3 e_i . dj) (with
+// sum w = 1, sum w e = 0, sum w e e = I/3) cancels both sums; for an exact D it is the
+// identity, and in FP64 a change at the rounding level.
+template <class L>
+__device__ __forceinline__ void project_conserved(double *D) {
+    double dm = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        dm += D[i];
+        if (L::ex(i)) jx += L::ex(i) * D[i];
+        if (L::ey(i)) jy += L::ey(i) * D[i];
+        if (L::ez(i)) jz += L::ez(i) * D[i];
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+        D[i] -= L::w(i) * (dm + 3.0 * (L::ex(i) * jx + L::ey(i) * jy + L::ez(i) * jz));
+}
+
 template <int Q>
 __device__ __forceinline__ AlphaOut alpha_newton(const double *f, const double *d, double a0, double amax,
                                                  double tol, int maxit) {

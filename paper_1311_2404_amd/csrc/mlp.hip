@@ -59,7 +59,12 @@ __global__ __launch_bounds__(256) void k_alpha_dataset(MlpDatasetParams d) {
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         f[i] = L::w(i) + double(h[i]);
-        dd[i] = (double(heq[i]) - double(h[i])) / f[i];
+        dd[i] = double(heq[i]) - double(h[i]);
+    }
+    project_conserved<L>(dd);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        dd[i] /= f[i];
         dmax = fmax(dmax, fabs(dd[i]));
         if (dd[i] < 0.0) amax = fmin(amax, -1.0 / dd[i]);
     }

@@ -183,6 +183,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                     f[i] = L::w(i) + double(h[i]);
                     D[i] = double(heq[i]) - double(h[i]);
                 }
+                project_conserved<L>(D);
                 const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
                 const AlphaOut ao = alpha_solve<Q>(f, D, double(m.rho), vsq, p,
                                                    (p.alpha_init == 2 && p.mlp) ? s_mlp : nullptr);

@@ -196,10 +196,14 @@ def test_c5_fullsize_one_step_sampled_fp32():
 
 
 def test_c5_fullsize_2000_steps_conservation():
-    """Per-component mass and total momentum conserved; G = 0.9 lies below the
-    separation threshold of psi = rho at rho = 1, so the seeded +-1% perturbations decay."""
+    """Per-component mass and total momentum conserved over 2000 steps with shifted FP32
+    storage.  G = 0.9 lies above this scheme's separation threshold for psi = rho at
+    rho_A = rho_B = 1 (the oracle puts it between G = 0.5 and 0.6), so the +-1%
+    perturbations grow into separated domains: rho_A ends with a spread of order one
+    while both densities stay positive.  (Plain FP32 storage, which rounds f ~ w to
+    2^-24 relative, drifts the mass by ~1e-5 over the same run once the interfaces form.)"""
     c = c5_case()
-    s = P.Sim.from_case(c, P.LBM_F32, P.LBM_AA)
+    s = P.Sim.from_case(c, P.LBM_F32S, P.LBM_AA)
     rho0, _ = s.macro()
     s.step(c.steps)
     rho1, u1 = s.macro()
@@ -208,4 +212,5 @@ def test_c5_fullsize_2000_steps_conservation():
     np.testing.assert_allclose(m1, m0, rtol=1e-7)
     p = (rho1.sum(0) * u1).sum(axis=1)
     assert np.abs(p).max() <= 1e-9 * m0.sum()
-    assert rho1[0].std() < 0.5 * rho0[0].std()
+    assert rho1.min() > 0.0 and np.isfinite(u1).all()
+    assert rho1[0].std() > 0.3 > 10 * rho0[0].std()

@@ -131,10 +131,10 @@ def test_trained_mlp_cuts_newton_iterations():
     feat = torch.cat(feats).contiguous()
     alpha = torch.cat(alphas).contiguous()
     ntr = int(0.9 * len(alpha))
-    P.lbm_mlp_set_weights(s.h, init_params(11, 0.1))
+    P.lbm_mlp_set_weights(s.h, P.mlp_initial_weights(11))
     loss = P.lbm_mlp_train(s.h, feat[:ntr].contiguous(), alpha[:ntr].contiguous(), ntr, 20, 4096, 1e-3, 5)
     assert loss[-1] < 0.05 * loss[0], loss
-    # held-out: the proposal is closer to the root than 2
+    # held-out: the proposal is closer to the root than 2 and than the bare series
     y = torch.empty(len(alpha) - ntr, dtype=torch.float32, device="cuda")
     P.lbm_mlp_forward(s.h, feat[ntr:].contiguous(), len(y), y)
     torch.cuda.synchronize()
@@ -144,7 +144,7 @@ def test_trained_mlp_cuts_newton_iterations():
     err_two = np.median(np.abs(2.0 - av))
     err_ser = np.median(np.abs(2 + (xv[:, 1] - 2 * xv[:, 2]) / 3 - av))
     print("held-out median |alpha0 - alpha|: 2 -> %.3e, series -> %.3e, MLP -> %.3e" % (err_two, err_ser, err_mlp))
-    assert err_mlp < 0.2 * err_two and err_mlp <= err_ser, (err_mlp, err_ser, err_two)
+    assert err_mlp < 0.05 * err_two and err_mlp <= 0.5 * err_ser, (err_mlp, err_ser, err_two)
 
     f0 = s.get_f()
     res = {}
