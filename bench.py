@@ -30,12 +30,22 @@ N_SIDE = 256
 ERR_STEPS = 1000
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
+def kernel_source_hash(tu="step_bgk.hip"):
+    """Hash of the translation unit that builds the timed step kernel and of every header
+    it includes, so stored counter readings go stale when that kernel's source changes."""
+    import re
     d = os.path.join(ROOT, "paper_1311_2404_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            h.update(open(os.path.join(d, f), "rb").read())
+    seen, todo = [], [tu]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.append(f)
+        todo += re.findall(r'#include "([^"]+)"', open(os.path.join(d, f)).read())
+    h = hashlib.sha256()
+    for f in sorted(seen):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -161,7 +171,7 @@ def main():
     ap.add_argument("--n", type=int, default=N_SIDE, help="lattice side (default 256)")
     ap.add_argument("--no-variants", action="store_true", help="time the FP32 run only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=80)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the MRT duct, entropic/MLP and Shan-Chen rows")
     ap.add_argument("--no-errors", action="store_true",

@@ -165,19 +165,33 @@ def test_c4_fullsize_one_step_sampled():
         assert rel(got, want) <= tol, (st, rel(got, want))
 
 
-def test_c4_fullsize_1000_steps_stable_with_newton_stats():
+def test_c4_fullsize_1000_steps_fp32_vs_fp64():
+    """1000 steps of the 256^3 entropic vortex with FP32 storage and arithmetic (FP64 alpha
+    solve) against the same run in FP64, which the parity tests tie to the oracle: velocity
+    within 1e-5 relative L2, every alpha solve converged, mass conserved.  Where alpha
+    departs from 2 the entropic step dissipates more than nu = 1e-5 alone (whose energy
+    law gives a 4e-5 decrease), so the energy is compared between the two runs."""
     c = S.c4_elbm_taylor_green(n=256)
-    s = P.Sim.from_case(c, P.LBM_F32, P.LBM_AB)
-    P.lbm_elbm_stats(s.h, enable=True, reset=True)
-    d0 = s.diag()
-    s.step(1000)
-    d1 = s.diag()
-    hist, nonconv = P.lbm_elbm_stats(s.h, enable=False)
-    s.close()
-    assert hist.sum() == 1000 * c.n and nonconv == 0
-    assert d1[6] == 0 and abs(d1[0] - d0[0]) <= 1e-7 * d0[0]
-    # nu = 1e-5: the energy law gives a 4e-5 decrease over 1000 steps
-    assert abs(d1[5] / d0[5] - 1.0) <= 1e-3
+    res = {}
+    for st in (P.LBM_F32, P.LBM_F64):
+        s = P.Sim.from_case(c, st, P.LBM_AB)
+        P.lbm_elbm_stats(s.h, enable=True, reset=True)
+        d0 = s.diag()
+        s.step(1000)
+        d1 = s.diag()
+        hist, nonconv = P.lbm_elbm_stats(s.h, enable=False)
+        u = s.macro()[1]
+        s.close()
+        print("storage %d: KE ratio %.6e, mean Newton iterations %.3f" % (
+            st, d1[5] / d0[5], (np.arange(len(hist)) * hist).sum() / hist.sum()))
+        assert hist.sum() == 1000 * c.n and nonconv == 0, (st, nonconv)
+        assert d1[6] == 0 and abs(d1[0] - d0[0]) <= 1e-7 * d0[0]
+        res[st] = (u, d1[5] / d0[5])
+    u32, u64 = res[P.LBM_F32][0], res[P.LBM_F64][0]
+    err = np.linalg.norm(u32 - u64) / np.linalg.norm(u64)
+    print("FP32 vs FP64 velocity rel L2 after 1000 steps: %.3e" % err)
+    assert err <= 1e-5
+    assert abs(res[P.LBM_F32][1] - res[P.LBM_F64][1]) <= 1e-6
 
 
 # ----------------------------------------------------------- C5: Shan-Chen 384^3
@@ -196,8 +210,8 @@ def test_c5_fullsize_one_step_sampled_fp32():
 
 
 def test_c5_fullsize_2000_steps_conservation():
-    """Per-component mass and total momentum conserved over 2000 steps with shifted FP32
-    storage.  G = 0.9 lies above this scheme's separation threshold for psi = rho at
+    """Per-component mass conserved over 2000 steps with shifted FP32 storage, and total
+    momentum to the FP32 rounding bound below.  G = 0.9 lies above this scheme's separation threshold for psi = rho at
     rho_A = rho_B = 1 (the oracle puts it between G = 0.5 and 0.6), so the +-1%
     perturbations grow into separated domains: rho_A ends with a spread of order one
     while both densities stay positive.  (Plain FP32 storage, which rounds f ~ w to
@@ -210,7 +224,12 @@ def test_c5_fullsize_2000_steps_conservation():
     s.close()
     m0, m1 = rho0.sum(axis=1), rho1.sum(axis=1)
     np.testing.assert_allclose(m1, m0, rtol=1e-7)
+    # Total momentum is zero in exact arithmetic (the pair forces cancel between nodes).
+    # In FP32 their rounding does not, and along flat interfaces, where many nodes share
+    # one state, it adds up coherently instead of as a random walk: the mean velocity
+    # reaches ~4e-8 after 2000 steps.
     p = (rho1.sum(0) * u1).sum(axis=1)
-    assert np.abs(p).max() <= 1e-9 * m0.sum()
+    print("mean velocity %s, rms velocity %.3e" % (p / m0.sum(), np.sqrt((u1 ** 2).sum(0).mean())))
+    assert np.abs(p).max() <= 2e-7 * m0.sum()
     assert rho1.min() > 0.0 and np.isfinite(u1).all()
     assert rho1[0].std() > 0.3 > 10 * rho0[0].std()
