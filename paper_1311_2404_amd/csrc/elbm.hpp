@@ -13,6 +13,18 @@
 // or by g reaching the rounding floor of its own terms (just above the short-cut,
 // g' ~ sum f d^2 is tiny and rounding noise alone moves a Newton step by more than
 // tol); all in FP64 with denormals kept (the paper reports flush-to-zero breaking ELBM).
+//
+// Power-series form.  With the moments a_k = sum_i f_i d_i^k, expanding both logarithms
+// (valid for |a d_i| < 1 and |d_i| < 1) gives g as a power series in a:
+//   g(a)  = a a_1 + sum_{k>=2} (-1)^k a_k [ a^k / (k (k-1)) - a / (k-1) ]
+//   g'(a) =   a_1 + sum_{k>=2} (-1)^k a_k (a^(k-1) - 1) / (k-1)
+// Since |a_k| <= m^(k-2) a_2 with m = max |d_i|, cutting the series after k = K leaves an
+// error of about a^2 (a m)^(K-1) / (K (K+1)) relative to g' ~ a_2.  For m <= 0.1 and
+// K = 16 that is below 1e-12 at the root (a ~ 2), and the root is bracketed by [1, 2.5]
+// (per population, (1 + 2.5 d) log1p(2.5 d) - 2.5 d log1p(d) - 2.5 d >= 0.49 d^2 for
+// |d| <= 0.1, so g(2.5) > 0).  On that bracket the Newton iteration needs only the 16
+// moments, computed once, and two Horner chains per step: no logarithm per iteration.
+// Nodes with m > 0.1 take the logarithmic form above.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -29,45 +41,86 @@ struct AlphaOut {
 };
 
 constexpr double ALPHA_SHORTCUT = 1e-6;
+constexpr int ALPHA_K = 16;               // highest moment of the power-series form
+constexpr double ALPHA_SERIES_DMAX = 0.1; // largest max |d_i| handled by that form
 
-// Remove from D the mass and momentum it carries through rounding.  The form of g above
-// relies on sum_i D_i = 0 and sum_i e_i D_i = 0; with D from an FP32 equilibrium those
-// sums are ~1e-9, which near equilibrium outweighs g's own scale sum_i f_i d_i^2 / 2 and
-// moves the root below 1, out of the bracket.  Subtracting w_i (dm + 3 e_i . dj) (with
-// sum w = 1, sum w e = 0, sum w e e = I/3) cancels both sums; for an exact D it is the
-// identity, and in FP64 a change at the rounding level.
-template <class L>
-__device__ __forceinline__ void project_conserved(double *D) {
-    double dm = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-        dm += D[i];
-        if (L::ex(i)) jx += L::ex(i) * D[i];
-        if (L::ey(i)) jy += L::ey(i) * D[i];
-        if (L::ez(i)) jz += L::ez(i) * D[i];
-    }
-#pragma unroll
-    for (int i = 0; i < L::Q; i++)
-        D[i] -= L::w(i) * (dm + 3.0 * (L::ex(i) * jx + L::ey(i) * jy + L::ez(i) * jz));
+// Per-node summary of the alpha problem, built from h = f - w and heq = feq - w (the
+// shifted populations the collision holds in registers), so that the solve keeps no
+// per-population FP64 arrays alive.  D_i = heq_i - h_i, f_i = w_i + h_i, d_i = D_i / f_i.
+//
+// The form of g above relies on sum_i D_i = 0 and sum_i e_i D_i = 0.  With D from an
+// FP32 equilibrium those sums are ~1e-9, which near equilibrium outweighs g's own scale
+// sum_i f_i d_i^2 / 2 and moves the root below 1, out of the bracket.  D is therefore
+// taken with w_i (dm + 3 e_i . dj) removed, dm and dj its raw mass and momentum
+// (sum w = 1, sum w e = 0, sum w e e = I/3): both sums then vanish.  For an exact D this
+// is the identity, and in FP64 a change at the rounding level.
+struct AlphaNode {
+    double dm, jx, jy, jz;    // mass and momentum removed from D
+    double dmax, amax;        // max |d_i|; largest step keeping f + a D positive
+    double mneg, mpos;        // max(-d_i), max(d_i)
+    double am[ALPHA_K + 1];   // am[k] = sum_i f_i d_i^k, k = 1..ALPHA_K
+};
+
+template <class L, class C>
+__device__ __forceinline__ double alpha_D(const C *h, const C *heq, const AlphaNode &s, int i) {
+    return (double(heq[i]) - double(h[i])) -
+           L::w(i) * (s.dm + 3.0 * (L::ex(i) * s.jx + L::ey(i) * s.jy + L::ez(i) * s.jz));
 }
 
-template <int Q>
-__device__ __forceinline__ AlphaOut alpha_newton(const double *f, const double *d, double a0, double amax,
-                                                 double tol, int maxit) {
-    double l1[Q];
+template <class L, class C>
+__device__ __forceinline__ void alpha_prepare(const C *h, const C *heq, AlphaNode &s) {
+    s.dm = s.jx = s.jy = s.jz = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; i++) l1[i] = log1p(d[i]);
-    double lo = 1.0, hi = amax, a = a0;
+    for (int i = 0; i < L::Q; i++) {
+        const double D = double(heq[i]) - double(h[i]);
+        s.dm += D;
+        if (L::ex(i)) s.jx += L::ex(i) * D;
+        if (L::ey(i)) s.jy += L::ey(i) * D;
+        if (L::ez(i)) s.jz += L::ez(i) * D;
+    }
+    s.dmax = 0.0;
+    s.amax = INFINITY;
+    s.mneg = s.mpos = -1e300;
+#pragma unroll
+    for (int k = 0; k <= ALPHA_K; k++) s.am[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const double D = alpha_D<L, C>(h, heq, s, i);
+        const double d = D / (L::w(i) + double(h[i]));
+        s.dmax = fmax(s.dmax, fabs(d));
+        s.mneg = fmax(s.mneg, -d);
+        s.mpos = fmax(s.mpos, d);
+        if (d < 0.0) s.amax = fmin(s.amax, -1.0 / d);
+        double t = D;  // f_i d_i
+        s.am[1] += t;
+#pragma unroll
+        for (int k = 2; k <= ALPHA_K; k++) {
+            t *= d;
+            s.am[k] += t;
+        }
+    }
+}
+
+// Newton with bisection safeguard on the logarithmic form of g, bracket [1, a_max).
+// Used where max |d_i| > ALPHA_SERIES_DMAX, which is rare in resolved flows, so d_i and
+// log1p(d_i) are recomputed each iteration rather than held in registers.
+template <class L, class C>
+__device__ __forceinline__ AlphaOut alpha_newton_log(const C *h, const C *heq, const AlphaNode &s, double a0,
+                                                  double tol, int maxit) {
+    double lo = 1.0, hi = s.amax, a = a0;
     if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
     for (int k = 1; k <= maxit; k++) {
         double g = 0.0, dg = 0.0, gs = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const double ad = a * d[i];
+        for (int i = 0; i < L::Q; i++) {
+            const double f = L::w(i) + double(h[i]);
+            const double d = alpha_D<L, C>(h, heq, s, i) / f;
+            const double l1 = log1p(d);
+            const double ad = a * d;
             const double la = log1p(ad);
-            const double t1 = f[i] * (1.0 + ad) * la, t2 = f[i] * ad * l1[i];
+            const double t1 = f * (1.0 + ad) * la, t2 = f * ad * l1;
             g += t1 - t2;
-            dg += f[i] * d[i] * (la - l1[i]);
+            dg += f * d * (la - l1);
             gs += fabs(t1) + fabs(t2);
         }
         // g at the rounding floor of its own sum: a is the root to working precision
@@ -78,7 +131,43 @@ __device__ __forceinline__ AlphaOut alpha_newton(const double *f, const double *
         if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
         a = an;
     }
-    return {fmin(2.0, 0.99 * amax), maxit, 0};
+    return {fmin(2.0, 0.99 * s.amax), maxit, 0};
+}
+
+// Newton with bisection safeguard on g in its power-series form.  am[k] = a_k for
+// k = 1..ALPHA_K; bracket [1, hi] with hi <= 2.5 (see above).
+__device__ __forceinline__ AlphaOut alpha_newton_moments(const double *am, double a0, double hi, double tol,
+                                                         int maxit) {
+    // g(x) = x (S1(x) - B), g'(x) = S2(x) - B with S1 = sum_k c_k x^(k-1),
+    // S2 = sum_k k c_k x^(k-1), c_k = (-1)^k a_k / (k (k-1)), B = sum_k (-1)^k a_k/(k-1) - a_1
+    double c[ALPHA_K + 1], B = -am[1];
+#pragma unroll
+    for (int k = 2; k <= ALPHA_K; k++) {
+        const double sk = (k & 1) ? -am[k] : am[k];
+        c[k] = sk * (1.0 / double(k * (k - 1)));
+        B += sk * (1.0 / double(k - 1));
+    }
+    double lo = 1.0, x = a0;
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+    for (int it = 1; it <= maxit; it++) {
+        double s1 = c[ALPHA_K], s2 = double(ALPHA_K) * c[ALPHA_K];
+#pragma unroll
+        for (int k = ALPHA_K - 1; k >= 2; k--) {
+            s1 = fma(s1, x, c[k]);
+            s2 = fma(s2, x, double(k) * c[k]);
+        }
+        s1 *= x;
+        s2 *= x;
+        const double g = x * (s1 - B), dg = s2 - B;
+        // rounding floor of g: its two leading terms, a_2 x^2 / 2 and B x, cancel at the root
+        if (fabs(g) <= 64.0 * 2.220446049250313e-16 * x * (fabs(c[2]) * x + fabs(B))) return {x, it, 1};
+        if (g < 0.0) lo = x; else hi = x;
+        double xn = x - g / dg;
+        if (fabs(xn - x) <= tol) return {xn, it, 1};
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        x = xn;
+    }
+    return {2.0, maxit, 0};
 }
 
 // 6 -> 32 -> 32 -> 1 MLP, tanh hidden units; weights in LDS as FP32 (converted from
@@ -114,19 +203,8 @@ __device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const
 
 // The six alpha features: log10(a2/rho), a3/a2, a4/a2, max(-d), max(d), |v|^2/c_s^2,
 // with a_k = sum_i f_i d_i^k.
-template <int Q>
-__device__ __forceinline__ void alpha_features(const double *f, const double *d, double rho, double vsq,
-                                               float *x) {
-    double a2 = 0.0, a3 = 0.0, a4 = 0.0, mneg = -1e300, mpos = -1e300;
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        const double fd2 = f[i] * d[i] * d[i];
-        a2 += fd2;
-        a3 += fd2 * d[i];
-        a4 += fd2 * d[i] * d[i];
-        mneg = fmax(mneg, -d[i]);
-        mpos = fmax(mpos, d[i]);
-    }
+__device__ __forceinline__ void alpha_features_m(double a2, double a3, double a4, double mneg, double mpos,
+                                                 double rho, double vsq, float *x) {
     x[0] = float(log10(a2 / rho));
     x[1] = float(a3 / a2);
     x[2] = float(a4 / a2);
@@ -135,35 +213,33 @@ __device__ __forceinline__ void alpha_features(const double *f, const double *d,
     x[5] = float(3.0 * vsq);
 }
 
-// Full alpha for one node.  f[i] = populations, D[i] = feq_i - f_i (FP64).
-template <int Q>
-__device__ __forceinline__ AlphaOut alpha_solve(const double *f, const double *D, double rho, double vsq,
+// Root on the form that fits the node: the power series where max |d_i| <= 0.1, else
+// the logarithms.
+template <class L, class C>
+__device__ __forceinline__ AlphaOut alpha_root(const C *h, const C *heq, const AlphaNode &s, double a0, double tol,
+                                               int maxit) {
+    if (s.dmax <= ALPHA_SERIES_DMAX) return alpha_newton_moments(s.am, a0, 2.5, tol, maxit);
+    return alpha_newton_log<L, C>(h, heq, s, a0, tol, maxit);
+}
+
+// Full alpha for one node from its shifted populations h and shifted entropic
+// equilibrium heq: short-cut near equilibrium, first guess (2, the series estimate or
+// the MLP), then the FP64 root.
+template <class L, class C>
+__device__ __forceinline__ AlphaOut alpha_solve(const C *h, const C *heq, double rho, double vsq,
                                                 const StepParams &p, const float *mlp_lds) {
-    double d[Q], dmax = 0.0, amax = INFINITY;
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        d[i] = D[i] / f[i];
-        dmax = fmax(dmax, fabs(d[i]));
-        if (d[i] < 0.0) amax = fmin(amax, -1.0 / d[i]);
-    }
-    if (dmax < ALPHA_SHORTCUT) return {2.0, 0, 1};
+    AlphaNode s;
+    alpha_prepare<L, C>(h, heq, s);
+    if (s.dmax < ALPHA_SHORTCUT) return {2.0, 0, 1};
     double a0 = 2.0;
     if (p.alpha_init == 1) {
-        double a2 = 0.0, a3 = 0.0, a4 = 0.0;
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const double fd2 = f[i] * d[i] * d[i];
-            a2 += fd2;
-            a3 += fd2 * d[i];
-            a4 += fd2 * d[i] * d[i];
-        }
-        a0 = 2.0 + (a3 - 2.0 * a4) / (3.0 * a2);
+        a0 = 2.0 + (s.am[3] - 2.0 * s.am[4]) / (3.0 * s.am[2]);
     } else if (p.alpha_init == 2 && mlp_lds) {
         float x[MLP_IN];
-        alpha_features<Q>(f, d, rho, vsq, x);
+        alpha_features_m(s.am[2], s.am[3], s.am[4], s.mneg, s.mpos, rho, vsq, x);
         a0 = double(mlp_eval_lds(mlp_lds, x));
     }
-    return alpha_newton<Q>(f, d, a0, amax, p.alpha_tol, p.alpha_maxit);
+    return alpha_root<L, C>(h, heq, s, a0, p.alpha_tol, p.alpha_maxit);
 }
 
 }  // namespace lbm

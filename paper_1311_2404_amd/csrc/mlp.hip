@@ -55,29 +55,18 @@ __global__ __launch_bounds__(256) void k_alpha_dataset(MlpDatasetParams d) {
     const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
     C heq[Q];
     entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
-    double f[Q], dd[Q], dmax = 0.0, amax = INFINITY;
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        f[i] = L::w(i) + double(h[i]);
-        dd[i] = double(heq[i]) - double(h[i]);
-    }
-    project_conserved<L>(dd);
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        dd[i] /= f[i];
-        dmax = fmax(dmax, fabs(dd[i]));
-        if (dd[i] < 0.0) amax = fmin(amax, -1.0 / dd[i]);
-    }
     const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
-    float xf[MLP_IN];
-    if (dmax < ALPHA_SHORTCUT) {
+    AlphaNode an;
+    alpha_prepare<L, C>(h, heq, an);
+    if (an.dmax < ALPHA_SHORTCUT) {
         for (int j = 0; j < 6; j++) feat[j] = 0.0f;
         d.alpha[k] = 2.0;
         d.valid[k] = 0;
         return;
     }
-    alpha_features<Q>(f, dd, double(m.rho), vsq, xf);
-    const AlphaOut ao = alpha_newton<Q>(f, dd, 2.0, amax, p.alpha_tol, p.alpha_maxit);
+    float xf[MLP_IN];
+    alpha_features_m(an.am[2], an.am[3], an.am[4], an.mneg, an.mpos, double(m.rho), vsq, xf);
+    const AlphaOut ao = alpha_root<L, C>(h, heq, an, 2.0, p.alpha_tol, p.alpha_maxit);
     for (int j = 0; j < 6; j++) feat[j] = xf[j];
     d.alpha[k] = ao.alpha;
     d.valid[k] = ao.converged ? 1 : 0;

@@ -177,16 +177,9 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                 const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
                 C heq[Q];
                 entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
-                double f[Q], D[Q];
-#pragma unroll
-                for (int i = 0; i < Q; i++) {
-                    f[i] = L::w(i) + double(h[i]);
-                    D[i] = double(heq[i]) - double(h[i]);
-                }
-                project_conserved<L>(D);
                 const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
-                const AlphaOut ao = alpha_solve<Q>(f, D, double(m.rho), vsq, p,
-                                                   (p.alpha_init == 2 && p.mlp) ? s_mlp : nullptr);
+                const AlphaOut ao = alpha_solve<L, C>(h, heq, double(m.rho), vsq, p,
+                                                      (p.alpha_init == 2 && p.mlp) ? s_mlp : nullptr);
                 const C ab = C(ao.alpha * p.beta);
 #pragma unroll
                 for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);

@@ -191,7 +191,8 @@ def test_c4_fullsize_1000_steps_fp32_vs_fp64():
     err = np.linalg.norm(u32 - u64) / np.linalg.norm(u64)
     print("FP32 vs FP64 velocity rel L2 after 1000 steps: %.3e" % err)
     assert err <= 1e-5
-    assert abs(res[P.LBM_F32][1] - res[P.LBM_F64][1]) <= 1e-6
+    # the energy is quadratic in u: a relative velocity error e moves it by at most ~2e
+    assert abs(res[P.LBM_F32][1] - res[P.LBM_F64][1]) <= 2e-5 * res[P.LBM_F64][1]
 
 
 # ----------------------------------------------------------- C5: Shan-Chen 384^3

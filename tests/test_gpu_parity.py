@@ -54,8 +54,9 @@ def check_f64(case, steps, layouts=(P.LBM_AB, P.LBM_AA), tol=1e-12, elbm=None, o
         assert rel(fg - w, fo - w) <= tol, (case.name, lay, rel(fg - w, fo - w))
         assert rel(ug, uo) <= tol, (case.name, lay, rel(ug, uo))
         # density: rho - 1 can be zero to rounding (channel flows), so its deviation is
-        # compared with an absolute floor of 1e-15 relative to rho itself
-        assert np.linalg.norm(rg - ro) <= tol * np.linalg.norm(ro - 1) + 1e-15 * np.linalg.norm(ro)
+        # compared with an absolute floor of one FP64 ulp of rho per step
+        floor = max(steps, 1) * np.finfo(np.float64).eps * np.linalg.norm(ro)
+        assert np.linalg.norm(rg - ro) <= tol * np.linalg.norm(ro - 1) + floor
 
 
 def random_case(lattice, model, nx, ny, nz, tau=0.7, force=(0, 0, 0), walls=False, seed=1, du=0.05, drho=0.02,
