@@ -9,11 +9,12 @@ namespace {
 
 dim3 flat_grid(uint32_t N, int bs) { return dim3((N + bs - 1) / bs); }
 
-__device__ __forceinline__ Geo geo_of(uint32_t n, int nx, int ny, int nz) {
+__device__ __forceinline__ Geo geo_of(uint32_t n, int nx, int ny, int nz, uint32_t rp, uint32_t rpitch,
+                                      int tyl) {
     const int x = int(n % uint32_t(nx));
     const int y = int((n / uint32_t(nx)) % uint32_t(ny));
     const int z = int(n / (uint32_t(nx) * uint32_t(ny)));
-    return make_geo(x, y, z, nx, ny, nz);
+    return make_geo(x, y, z, nx, ny, nz, rp, rpitch, tyl);
 }
 
 // f_eq(rho, u)_i - w_i in FP64: the polynomial equilibrium of section 2, or the entropic one.
@@ -52,7 +53,7 @@ __global__ void k_init_plane(PlaneParams p) {
     using C = typename St::C;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= p.N) return;
-    const Geo g = geo_of(n, p.nx, p.ny, p.nz);
+    const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     const double ux = p.u[n], uy = p.u[p.N + n], uz = L::D == 3 ? p.u[2 * size_t(p.N) + n] : 0.0;
     double h = heq_plane<L>(p.q, p.rho[n], ux, uy, uz, p.entropic);
     if (p.df) h += p.df[n];
@@ -75,7 +76,7 @@ __global__ void k_get_plane(PlaneParams p) {
     using C = typename St::C;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= p.N) return;
-    const Geo g = geo_of(n, p.nx, p.ny, p.nz);
+    const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     int slot;
     uint32_t nd;
     canon_loc_rt<L>(p.layout, p.q, g, slot, nd);
@@ -95,7 +96,7 @@ __global__ void k_set_plane(PlaneParams p) {
     using C = typename St::C;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= p.N) return;
-    const Geo g = geo_of(n, p.nx, p.ny, p.nz);
+    const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     int slot;
     uint32_t nd;
     canon_loc_rt<L>(p.layout, p.q, g, slot, nd);
@@ -116,7 +117,7 @@ __global__ void k_macro(MacroParams p) {
     using C = typename St::C;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= p.N) return;
-    const Geo g = geo_of(n, p.nx, p.ny, p.nz);
+    const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
     for (int c = 0; c < p.ncomp; c++) {
         const T *pop = static_cast<const T *>(p.pop) + size_t(c) * L::Q * p.S;

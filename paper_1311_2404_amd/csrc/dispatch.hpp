@@ -67,6 +67,9 @@ struct PlaneParams {
     int nx, ny, nz;
     uint32_t N;
     uint32_t S;        // population stride (elements)
+    uint32_t rp;       // population tile pitch (elements)
+    uint32_t rpitch;   // population row pitch inside a tile (elements)
+    int tyl;           // log2 of the rows per tile
     int layout;        // LAYOUT_* of the state being accessed
     int comp, q;       // component and population index of the plane
     void *pop;         // population array (all components)
@@ -84,6 +87,9 @@ struct MacroParams {
     int nx, ny, nz;
     uint32_t N;
     uint32_t S;        // population stride (elements)
+    uint32_t rp;       // population tile pitch (elements)
+    uint32_t rpitch;   // population row pitch inside a tile (elements)
+    int tyl;           // log2 of the rows per tile
     int layout, model, ncomp;
     const void *pop;
     const uint8_t *flags;

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_alpha_dataset(MlpDatasetParams d) {
     const uint32_t n = uint32_t(mix64(d.seed ^ uint64_t(k)) % uint64_t(p.N));
     const int x = int(n % uint32_t(p.nx)), y = int((n / uint32_t(p.nx)) % uint32_t(p.ny));
     const int z = int(n / (uint32_t(p.nx) * uint32_t(p.ny)));
-    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     float *feat = d.feat + 6 * k;
     if (p.flags && p.flags[n] == 1) {
         for (int j = 0; j < 6; j++) feat[j] = 0.0f;

@@ -24,15 +24,29 @@
 #include "params.hpp"
 #include "storage.hpp"
 
-// Population loads and stores of the step kernels.  Stores carry the non-temporal hint
-// (every post-collision value is read back only in the next step, after ~2.5 GB of other
-// traffic): measured +5% on the 256^3 FP32 step.  Build variants: LBM_NT_LOADS adds the
-// hint to loads, LBM_PLAIN_STORES removes it from stores.
-#if defined(LBM_NT_LOADS)
-#define LBM_LOAD(ptr) __builtin_nontemporal_load(ptr)
+// Population loads and stores of the step kernels carry the non-temporal hint: every
+// value is read once per step and written once, and is next touched only after ~2.5 GB
+// of other traffic.  Measured on the 256^3 step: +5% for FP32 stores.  Loads take it
+// where it pays:
+//  - AB: only populations with e_x = 0.  A wave's pull of an x-moving population starts
+//    one element off its 256-byte segment, so one 128-byte line is shared with the
+//    neighbouring wave; marked non-temporal, that line is often gone before the
+//    neighbour reads it (FETCH_SIZE 7.5% above the algorithmic bytes; exact without).
+//    +0.8% over hinting every load.
+//  - AA: every load (+7% over none, despite the refetch).
+//  - 2-byte elements: none (the hint costs them 3-4%).
+// Build variants: LBM_PLAIN_LOADS and LBM_PLAIN_STORES remove the hint.
+template <class L, int LAYOUT, class T>
+__device__ __forceinline__ T pop_load(const T *ptr, int i) {
+#if defined(LBM_PLAIN_LOADS)
+    return *ptr;
 #else
-#define LBM_LOAD(ptr) (*(ptr))
+    if constexpr (sizeof(T) < 4) return *ptr;
+    if (LAYOUT == lbm::LAYOUT_AB && L::ex(i) != 0) return *ptr;
+    return __builtin_nontemporal_load(ptr);
 #endif
+}
+#define LBM_LOAD(ptr, i) pop_load<L, LAYOUT>((ptr), (i))
 #if defined(LBM_PLAIN_STORES)
 #define LBM_STORE(ptr, v) (*(ptr) = (v))
 #else
@@ -41,18 +55,27 @@
 
 namespace lbm {
 
+// A node and its periodic neighbours.  at() is the linear node index (flags, psi,
+// macroscopic fields); pa() is the node's offset inside one population's block, which
+// differs from at() in the row-interleaved population layouts (tiles of 2^tyl rows).
 struct Geo {
     int x, y, z, xm, xp, ym, yp, zm, zp;
-    uint32_t nx, ny;
+    uint32_t nx, ny, rp, rpitch;
+    int tyl;
+    __device__ __forceinline__ uint32_t y_of(int dy) const { return uint32_t(dy == 0 ? y : (dy > 0 ? yp : ym)); }
+    __device__ __forceinline__ uint32_t z_of(int dz) const { return uint32_t(dz == 0 ? z : (dz > 0 ? zp : zm)); }
+    __device__ __forceinline__ uint32_t x_of(int dx) const { return uint32_t(dx == 0 ? x : (dx > 0 ? xp : xm)); }
     __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const {
-        const int xx = dx == 0 ? x : (dx > 0 ? xp : xm);
-        const int yy = dy == 0 ? y : (dy > 0 ? yp : ym);
-        const int zz = dz == 0 ? z : (dz > 0 ? zp : zm);
-        return (uint32_t(zz) * ny + uint32_t(yy)) * nx + uint32_t(xx);
+        return (z_of(dz) * ny + y_of(dy)) * nx + x_of(dx);
+    }
+    __device__ __forceinline__ uint32_t pa(int dx, int dy, int dz) const {
+        const uint32_t yy = y_of(dy);
+        return (z_of(dz) * (ny >> tyl) + (yy >> tyl)) * rp + (yy & ((1u << tyl) - 1u)) * rpitch + x_of(dx);
     }
 };
 
-__device__ __forceinline__ Geo make_geo(int x, int y, int z, int nx, int ny, int nz) {
+__device__ __forceinline__ Geo make_geo(int x, int y, int z, int nx, int ny, int nz, uint32_t rp,
+                                        uint32_t rpitch, int tyl) {
     Geo g;
     g.x = x;
     g.y = y;
@@ -65,18 +88,21 @@ __device__ __forceinline__ Geo make_geo(int x, int y, int z, int nx, int ny, int
     g.zp = (z + 1 == nz) ? 0 : z + 1;
     g.nx = uint32_t(nx);
     g.ny = uint32_t(ny);
+    g.rp = rp;
+    g.rpitch = rpitch;
+    g.tyl = tyl;
     return g;
 }
 
-// Where the physical population f_i(x) currently lives (slot, node).
+// Where the physical population f_i(x) currently lives (slot, offset in the slot's block).
 template <class L>
 __device__ __forceinline__ void canon_loc(int layout, int i, const Geo &g, int &slot, uint32_t &node) {
     if (layout == LAYOUT_AA_EVEN) {
         slot = i;
-        node = g.at(0, 0, 0);
+        node = g.pa(0, 0, 0);
     } else {
         slot = layout == LAYOUT_AB ? i : opp(i);
-        node = g.at(-L::ex(i), -L::ey(i), -L::ez(i));
+        node = g.pa(-L::ex(i), -L::ey(i), -L::ez(i));
     }
 }
 
@@ -85,13 +111,13 @@ template <class L>
 __device__ __forceinline__ void post_loc(int layout, int i, const Geo &g, int &slot, uint32_t &node) {
     if (layout == LAYOUT_AB) {
         slot = i;
-        node = g.at(0, 0, 0);
+        node = g.pa(0, 0, 0);
     } else if (layout == LAYOUT_AA_EVEN) {
         slot = opp(i);
-        node = g.at(0, 0, 0);
+        node = g.pa(0, 0, 0);
     } else {
         slot = i;
-        node = g.at(L::ex(i), L::ey(i), L::ez(i));
+        node = g.pa(L::ex(i), L::ey(i), L::ez(i));
     }
 }
 
@@ -143,7 +169,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
 
     const bool active = x < p.nx && y < p.ny;
     if (active) {
-        const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
+        const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
         const uint32_t n = g.at(0, 0, 0);
         const uint32_t S = p.S;
         // no __restrict__: with AA the two pointers are the same copy
@@ -155,7 +181,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             int slot;
             uint32_t nd;
             canon_loc<L>(LAYOUT, i, g, slot, nd);
-            raw[i] = LBM_LOAD(src + size_t(slot) * S + nd);
+            raw[i] = LBM_LOAD(src + size_t(slot) * S + nd, i);
         }
         T out[Q];
         const bool wall = FLAGS && p.flags[n] == 1;
@@ -225,7 +251,7 @@ __global__ __launch_bounds__(512) void k_psi(StepParams p) {
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= p.nx || y >= p.ny) return;
-    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     const uint32_t n = g.at(0, 0, 0);
     const T *src = static_cast<const T *>(p.src);
     C *psi = static_cast<C *>(const_cast<void *>(p.psi));
@@ -256,7 +282,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= p.nx || y >= p.ny) return;
-    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz);
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     const uint32_t n = g.at(0, 0, 0);
     const uint32_t N = p.N, S = p.S;
     const T *src = static_cast<const T *>(p.src);
@@ -272,7 +298,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
             int slot;
             uint32_t nd;
             canon_loc<L>(LAYOUT, i, g, slot, nd);
-            h[c][i] = St::decode(LBM_LOAD(src + (size_t(c) * Q + slot) * S + nd), C(L::w(i)));
+            h[c][i] = St::decode(LBM_LOAD(src + (size_t(c) * Q + slot) * S + nd, i), C(L::w(i)));
         }
         m[c] = moments<L, C>(h[c]);
     }

@@ -35,12 +35,14 @@ __global__ __launch_bounds__(256) void k_step_vec(StepParams p) {
     auto row = [&](int dy, int dz) -> uint32_t {
         const int yy = dy == 0 ? y : (dy > 0 ? yp : ym);
         const int zz = dz == 0 ? z : (dz > 0 ? zp : zm);
-        return (uint32_t(zz) * uint32_t(p.ny) + uint32_t(yy)) * uint32_t(p.nx);
+        const uint32_t uy = uint32_t(yy);  // offset of the row in a population block
+        return (uint32_t(zz) * (uint32_t(p.ny) >> p.tyl) + (uy >> p.tyl)) * p.rp + (uy & ((1u << p.tyl) - 1u)) * p.rpitch;
     };
     const T *src = static_cast<const T *>(p.src);
     T *dst = static_cast<T *>(p.dst);
     const uint32_t S = p.S;
-    const uint32_t own = row(0, 0) + uint32_t(x0);
+    const uint32_t own = row(0, 0) + uint32_t(x0);                                         // population offset
+    const uint32_t own_n = (uint32_t(z) * uint32_t(p.ny) + uint32_t(y)) * uint32_t(p.nx) + uint32_t(x0);  // node index
 
     // gather: raw[i][v] is population i arriving at node x0 + v
     T raw[Q][VEC];
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(256) void k_step_vec(StepParams p) {
     T out[Q][VEC];
 #pragma unroll
     for (int v = 0; v < VEC; v++) {
-        const bool wall = FLAGS && p.flags[own + v] == 1;
+        const bool wall = FLAGS && p.flags[own_n + v] == 1;
         if (wall) {
 #pragma unroll
             for (int i = 0; i < Q; i++) out[i][v] = raw[opp(i)][v];
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(256) void k_step_vec(StepParams p) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             uint32_t rnd = 0;
-            if constexpr (sizeof(T) == 2) rnd = sr_bits<St>(p, own + v, i, key);
+            if constexpr (sizeof(T) == 2) rnd = sr_bits<St>(p, own_n + v, i, key);
             out[i][v] = St::encode(o[i], C(L::w(i)), rnd);
         }
     }

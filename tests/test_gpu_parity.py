@@ -177,6 +177,49 @@ def test_aa_equals_ab_bitwise(storage, steps):
     assert np.array_equal(fa, fb) and np.array_equal(ua, ub)
 
 
+_LAYOUT_ENVS = [
+    {"LBM_POP_LAYOUT": "soa"},
+    {"LBM_POP_LAYOUT": "soa", "LBM_POP_PAD": "0"},
+    {"LBM_POP_LAYOUT": "rows", "LBM_BLOCK_PAD": "0"},
+    {"LBM_POP_LAYOUT": "rows", "LBM_ROW_PAD": "768", "LBM_BLOCK_PAD": "2560"},
+    {"LBM_POP_LAYOUT": "rows", "LBM_ROW_TILE": "2"},
+    {"LBM_POP_LAYOUT": "rows", "LBM_ROW_TILE": "8", "LBM_BLOCK_PAD": "0"},  # 8 does not divide ny: 4
+]
+_LAYOUT_KEYS = ("LBM_POP_LAYOUT", "LBM_POP_PAD", "LBM_ROW_PAD", "LBM_BLOCK_PAD", "LBM_ROW_TILE")
+
+
+@pytest.mark.parametrize("model", [S.BGK, S.MRT, S.SHANCHEN, S.ELBM])
+def test_population_layouts_agree_bitwise(model, monkeypatch):
+    """The population layout in HBM (SoA or row-interleaved, tiled or not, with any padding) only moves
+    where each value lives: every layout gives the same fields bit for bit, for AB and AA
+    streaming, on a ragged box with walls (walls and force where the model takes them)."""
+    nx, ny, nz = 37, 12, 6
+    kw = {}
+    if model == S.MRT:
+        kw = dict(force=(1e-5, 0, 2e-5), walls=True, mrt_rates=S.mrt_rates_d3q19(1 / 0.6, 1.2), tau=0.6)
+    elif model == S.BGK:
+        kw = dict(force=(2e-5, -1e-5, 0), walls=True)
+    elif model == S.SHANCHEN:
+        kw = dict(tau=0.9, G=0.9, psi=0, du=0.02, drho=0.05)
+    else:
+        kw = dict(tau=0.51, du=0.06, noise=2e-2)
+    c = random_case(S.D3Q19, model, nx, ny, nz, **kw)
+    storages = [P.LBM_F64, P.LBM_F32] + ([P.LBM_BF16S] if model in (S.BGK, S.MRT) else [])
+    for st in storages:
+        for lay in (P.LBM_AB, P.LBM_AA):
+            ref = gpu_run(c, 5, st, lay)
+            for env in _LAYOUT_ENVS:
+                for k in _LAYOUT_KEYS:
+                    monkeypatch.delenv(k, raising=False)
+                for k, v in env.items():
+                    monkeypatch.setenv(k, v)
+                got = gpu_run(c, 5, st, lay)
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b), (model, st, lay, env)
+            for k in _LAYOUT_KEYS:
+                monkeypatch.delenv(k, raising=False)
+
+
 @pytest.mark.parametrize("storage", [P.LBM_F64, P.LBM_F32])
 def test_checkpoint_resume_bitwise(storage):
     c = random_case(S.D3Q19, S.BGK, 33, 9, 8, force=(1e-5, 0, 0), walls=True)
