@@ -145,16 +145,16 @@ def run_extras(P, S, stream, torch):
     print("[bench] ELBM done", file=sys.stderr, flush=True)
 
     # D3Q19 two-component Shan-Chen 384^3, FP32 compute: throughput and per-component
-    # conservation, with plain and with shifted FP32 storage (same bytes per node)
+    # conservation with plain and shifted FP32 storage (same bytes per node), AB and AA
     c5 = S.c5_shan_chen(n=384)
-    for st, tag in [(P.LBM_F32, "fp32"), (P.LBM_F32S, "f32s")]:
-        s = P.Sim.from_case(c5, st, P.LBM_AA, stream=stream)
+    for st, lay, tag in [(P.LBM_F32, P.LBM_AB, "fp32"), (P.LBM_F32, P.LBM_AA, "fp32_aa"), (P.LBM_F32S, P.LBM_AB, "f32s")]:
+        s = P.Sim.from_case(c5, st, lay, stream=stream)
         d0 = s.diag()
         ms = _time_steps(s, stream, torch, 100)
         d1 = s.diag()
         s.close()
         out["d3q19_shan_chen_384_" + tag] = {"mlups": round(c5.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
-                                             "bytes_per_node": 472,
+                                             "layout": "aa" if lay == P.LBM_AA else "ab", "bytes_per_node": 472,
                                              "hbm_gbs_algorithmic": round(472 * c5.n / (ms * 1e-3) / 1e9, 1),
                                              "steps": 100,
                                              "mass_rel_change": [float(abs(d1[c] - d0[c]) / d0[c]) for c in (0, 1)]}

@@ -223,9 +223,9 @@ __device__ __forceinline__ AlphaOut alpha_root(const C *h, const C *heq, const A
 }
 
 // Full alpha for one node from its shifted populations h and shifted entropic
-// equilibrium heq: short-cut near equilibrium, first guess (2, the series estimate or
-// the MLP), then the FP64 root.
-template <class L, class C>
+// equilibrium heq: short-cut near equilibrium, first guess (2, the series estimate or,
+// in the kernel built with MLP, the network's proposal), then the FP64 root.
+template <class L, class C, bool MLP>
 __device__ __forceinline__ AlphaOut alpha_solve(const C *h, const C *heq, double rho, double vsq,
                                                 const StepParams &p, const float *mlp_lds) {
     AlphaNode s;
@@ -234,7 +234,7 @@ __device__ __forceinline__ AlphaOut alpha_solve(const C *h, const C *heq, double
     double a0 = 2.0;
     if (p.alpha_init == 1) {
         a0 = 2.0 + (s.am[3] - 2.0 * s.am[4]) / (3.0 * s.am[2]);
-    } else if (p.alpha_init == 2 && mlp_lds) {
+    } else if constexpr (MLP) {
         float x[MLP_IN];
         alpha_features_m(s.am[2], s.am[3], s.am[4], s.mneg, s.mpos, rho, vsq, x);
         a0 = double(mlp_eval_lds(mlp_lds, x));

@@ -5,7 +5,9 @@
 namespace lbm {
 
 enum Layout { LAYOUT_AB = 0, LAYOUT_AA_EVEN = 1, LAYOUT_AA_ODD = 2 };
-enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3 };
+// M_ELBM_MLP: the entropic step built with the MLP first guess (a kernel of its own, so
+// that the network's registers do not weigh on the step without it)
+enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3, M_ELBM_MLP = 4 };
 
 constexpr int MLP_IN = 6;
 constexpr int MLP_H = 32;

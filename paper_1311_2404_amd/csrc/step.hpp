@@ -155,16 +155,17 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     const int nthr = blockDim.x * blockDim.y;
 
     // ELBM only: MLP weights (FP32 from BF16) and the Newton-iteration histogram in LDS
-    __shared__ float s_mlp[MODEL == M_ELBM ? MLP_NTOTAL : 1];
-    __shared__ uint32_t s_hist[MODEL == M_ELBM ? NEWTON_BINS + 1 : 1];
-    if constexpr (MODEL == M_ELBM) {
-        if (p.alpha_init == 2 && p.mlp) {
+    constexpr bool ELBM = MODEL == M_ELBM || MODEL == M_ELBM_MLP;
+    __shared__ float s_mlp[MODEL == M_ELBM_MLP ? MLP_NTOTAL : 1];
+    __shared__ uint32_t s_hist[ELBM ? NEWTON_BINS + 1 : 1];
+    if constexpr (ELBM) {
+        if constexpr (MODEL == M_ELBM_MLP) {
             for (int k = tid; k < MLP_NPARAM; k += nthr) s_mlp[k] = __uint_as_float(uint32_t(p.mlp[k]) << 16);
             for (int k = tid; k < MLP_NNORM; k += nthr) s_mlp[MLP_NPARAM + k] = p.mlp_norm[k];
         }
         if (p.stats)
             for (int k = tid; k < NEWTON_BINS + 1; k += nthr) s_hist[k] = 0u;
-        if ((p.alpha_init == 2 && p.mlp) || p.stats) __syncthreads();
+        if (MODEL == M_ELBM_MLP || p.stats) __syncthreads();
     }
 
     const bool active = x < p.nx && y < p.ny;
@@ -204,8 +205,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                 C heq[Q];
                 entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
                 const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
-                const AlphaOut ao = alpha_solve<L, C>(h, heq, double(m.rho), vsq, p,
-                                                      (p.alpha_init == 2 && p.mlp) ? s_mlp : nullptr);
+                const AlphaOut ao = alpha_solve<L, C, MODEL == M_ELBM_MLP>(h, heq, double(m.rho), vsq, p, s_mlp);
                 const C ab = C(ao.alpha * p.beta);
 #pragma unroll
                 for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             LBM_STORE(dst + size_t(slot) * S + nd, out[i]);
         }
     }
-    if constexpr (MODEL == M_ELBM) {
+    if constexpr (ELBM) {
         if (p.stats) {
             __syncthreads();
             for (int k = tid; k < NEWTON_BINS + 1; k += nthr)

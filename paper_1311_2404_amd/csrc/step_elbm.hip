@@ -12,8 +12,13 @@ hipError_t launch_step_elbm(int lattice, int storage, int layout, bool flags, co
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
-                if (flags) k_step<L, St, M_ELBM, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
-                else k_step<L, St, M_ELBM, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                if (p.alpha_init == 2 && p.mlp) {
+                    if (flags) k_step<L, St, M_ELBM_MLP, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
+                    else k_step<L, St, M_ELBM_MLP, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                } else {
+                    if (flags) k_step<L, St, M_ELBM, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
+                    else k_step<L, St, M_ELBM, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                }
                 return hipGetLastError();
             });
         });
