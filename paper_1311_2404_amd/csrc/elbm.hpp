@@ -170,13 +170,23 @@ __device__ __forceinline__ AlphaOut alpha_newton_moments(const double *am, doubl
     return {2.0, maxit, 0};
 }
 
-// 6 -> 32 -> 32 -> 1 MLP, tanh hidden units; weights in LDS as FP32 (converted from
-// the BF16 copy), FP32 accumulation.  Layout: W1[32][6], b1[32], W2[32][32], b2[32],
-// w3[32], b3, then the FP32 input normalisation mu[6], isd[6]: the network sees
-// (x - mu) * isd.  Its output is added to the series estimate of the root,
-// 2 + (x1 - 2 x2)/3 = 2 + (a3 - 2 a4)/(3 a2), so it only carries the series' residual
-// (which BF16 weights can represent to far better absolute accuracy than alpha - 2).
-__device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const float *xraw) {
+// tanh from the identity tanh x = 1 - 2 / (e^(2x) + 1), with the hardware base-2
+// exponential and reciprocal (absolute error ~2e-7; +-1 in the limits, where e^(2x)
+// overflows to inf or underflows to 0).  Used for inference only; training keeps tanhf.
+__device__ __forceinline__ float tanh_fast(float x) {
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e)
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+// 6 -> 32 -> 32 -> 1 MLP, tanh hidden units, FP32 accumulation.  W holds the BF16
+// weights widened to FP32 (the same values) followed by the FP32 input normalisation:
+// W1[32][6], b1[32], W2[32][32], b2[32], w3[32], b3, mu[6], isd[6]; the network sees
+// (x - mu) * isd.  W is read with lane-uniform addresses, so the weights come through
+// scalar loads and feed the FMAs from scalar registers.  The output is added to the
+// series estimate of the root, 2 + (x1 - 2 x2)/3 = 2 + (a3 - 2 a4)/(3 a2), so the
+// network only carries the series' residual (which BF16 weights can represent to far
+// better absolute accuracy than alpha - 2).
+__device__ __forceinline__ float mlp_eval(const float *__restrict__ W, const float *xraw) {
     float x[MLP_IN];
 #pragma unroll
     for (int k = 0; k < MLP_IN; k++) x[k] = (xraw[k] - W[MLP_NPARAM + k]) * W[MLP_NPARAM + MLP_IN + k];
@@ -188,7 +198,7 @@ __device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const
         float s = b1[j];
 #pragma unroll
         for (int k = 0; k < MLP_IN; k++) s = fmaf(W1[j * MLP_IN + k], x[k], s);
-        h1[j] = tanhf(s);
+        h1[j] = tanh_fast(s);
     }
     float y = b3[0];
 #pragma unroll 4
@@ -196,7 +206,7 @@ __device__ __forceinline__ float mlp_eval_lds(const float *__restrict__ W, const
         float s = b2[j];
 #pragma unroll
         for (int k = 0; k < MLP_H; k++) s = fmaf(W2[j * MLP_H + k], h1[k], s);
-        y = fmaf(w3[j], tanhf(s), y);
+        y = fmaf(w3[j], tanh_fast(s), y);
     }
     return (2.0f + (xraw[1] - 2.0f * xraw[2]) * (1.0f / 3.0f)) + y;
 }
@@ -227,7 +237,7 @@ __device__ __forceinline__ AlphaOut alpha_root(const C *h, const C *heq, const A
 // in the kernel built with MLP, the network's proposal), then the FP64 root.
 template <class L, class C, bool MLP>
 __device__ __forceinline__ AlphaOut alpha_solve(const C *h, const C *heq, double rho, double vsq,
-                                                const StepParams &p, const float *mlp_lds) {
+                                                const StepParams &p, const float *__restrict__ mlp_w) {
     AlphaNode s;
     alpha_prepare<L, C>(h, heq, s);
     if (s.dmax < ALPHA_SHORTCUT) return {2.0, 0, 1};
@@ -237,7 +247,7 @@ __device__ __forceinline__ AlphaOut alpha_solve(const C *h, const C *heq, double
     } else if constexpr (MLP) {
         float x[MLP_IN];
         alpha_features_m(s.am[2], s.am[3], s.am[4], s.mneg, s.mpos, rho, vsq, x);
-        a0 = double(mlp_eval_lds(mlp_lds, x));
+        a0 = double(mlp_eval(mlp_w, x));
     }
     return alpha_root<L, C>(h, heq, s, a0, p.alpha_tol, p.alpha_maxit);
 }

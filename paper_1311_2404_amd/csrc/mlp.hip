@@ -72,17 +72,13 @@ __global__ __launch_bounds__(256) void k_alpha_dataset(MlpDatasetParams d) {
     d.valid[k] = ao.converged ? 1 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_forward_bf16(const uint16_t *wb, const float *norm, const float *x,
-                                                         int64_t n, float *y) {
-    __shared__ float s_w[MLP_NTOTAL];
-    for (int k = threadIdx.x; k < MLP_NPARAM; k += blockDim.x) s_w[k] = __uint_as_float(uint32_t(wb[k]) << 16);
-    for (int k = threadIdx.x; k < MLP_NNORM; k += blockDim.x) s_w[MLP_NPARAM + k] = norm[k];
-    __syncthreads();
+__global__ __launch_bounds__(256) void k_mlp_forward_bf16(const float *__restrict__ wf, const float *x, int64_t n,
+                                                         float *y) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
     float xr[MLP_IN];
     for (int j = 0; j < MLP_IN; j++) xr[j] = x[MLP_IN * r + j];
-    y[r] = mlp_eval_lds(s_w, xr);
+    y[r] = mlp_eval(wf, xr);
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -210,10 +206,17 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, float b1t, 
     w[k] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-__global__ void k_to_bf16(const float *w, uint16_t *wb) {
+// BF16 inference weights, and the same values widened to FP32 followed by the input
+// normalisation (the layout mlp_eval reads)
+__global__ void k_to_bf16(const float *w, const float *norm, uint16_t *wb, float *wf) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= MLP_NPARAM) return;
-    wb[k] = __builtin_bit_cast(uint16_t, static_cast<__bf16>(w[k]));
+    if (k < MLP_NPARAM) {
+        const uint16_t b = __builtin_bit_cast(uint16_t, static_cast<__bf16>(w[k]));
+        wb[k] = b;
+        wf[k] = __uint_as_float(uint32_t(b) << 16);
+    } else if (k < MLP_NTOTAL) {
+        wf[k] = norm[k - MLP_NPARAM];
+    }
 }
 
 // sums and sums of squares of the series residual alpha - (2 + (x1 - 2 x2)/3)
@@ -289,10 +292,9 @@ hipError_t launch_alpha_dataset(int lattice, int storage, const MlpDatasetParams
     });
 }
 
-hipError_t mlp_forward_bf16(const uint16_t *w, const float *norm, const float *x, int64_t n, float *y,
-                            hipStream_t s) {
+hipError_t mlp_forward_bf16(const float *wf, const float *x, int64_t n, float *y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_mlp_forward_bf16<<<dim3(uint32_t((n + 255) / 256)), 256, 0, s>>>(w, norm, x, n, y);
+    k_mlp_forward_bf16<<<dim3(uint32_t((n + 255) / 256)), 256, 0, s>>>(wf, x, n, y);
     return hipGetLastError();
 }
 
@@ -312,8 +314,8 @@ hipError_t mlp_adam(float *w, const float *grad, float *m, float *v, int t, floa
     return hipGetLastError();
 }
 
-hipError_t mlp_to_bf16(const float *w, uint16_t *wb, hipStream_t s) {
-    k_to_bf16<<<(MLP_NPARAM + 255) / 256, 256, 0, s>>>(w, wb);
+hipError_t mlp_to_bf16(const float *w, const float *norm, uint16_t *wb, float *wf, hipStream_t s) {
+    k_to_bf16<<<(MLP_NTOTAL + 255) / 256, 256, 0, s>>>(w, norm, wb, wf);
     return hipGetLastError();
 }
 

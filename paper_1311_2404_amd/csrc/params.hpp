@@ -39,7 +39,7 @@ struct StepParams {
     int alpha_maxit;
     int alpha_init;             // 0: 2, 1: series, 2: MLP
     const uint16_t *mlp;        // bf16 MLP weights (alpha_init == 2)
-    const float *mlp_norm;      // FP32 input normalisation mu[6], isd[6]
+    const float *mlp_wf;        // the same weights widened to FP32, then mu[6], isd[6]
     unsigned long long *stats;  // [NEWTON_BINS] histogram + [1] non-converged, or nullptr
     // Shan-Chen
     const void *psi;            // psi[2][N] in compute precision

@@ -154,18 +154,14 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const int nthr = blockDim.x * blockDim.y;
 
-    // ELBM only: MLP weights (FP32 from BF16) and the Newton-iteration histogram in LDS
+    // ELBM only: the Newton-iteration histogram in LDS
     constexpr bool ELBM = MODEL == M_ELBM || MODEL == M_ELBM_MLP;
-    __shared__ float s_mlp[MODEL == M_ELBM_MLP ? MLP_NTOTAL : 1];
     __shared__ uint32_t s_hist[ELBM ? NEWTON_BINS + 1 : 1];
     if constexpr (ELBM) {
-        if constexpr (MODEL == M_ELBM_MLP) {
-            for (int k = tid; k < MLP_NPARAM; k += nthr) s_mlp[k] = __uint_as_float(uint32_t(p.mlp[k]) << 16);
-            for (int k = tid; k < MLP_NNORM; k += nthr) s_mlp[MLP_NPARAM + k] = p.mlp_norm[k];
-        }
-        if (p.stats)
+        if (p.stats) {
             for (int k = tid; k < NEWTON_BINS + 1; k += nthr) s_hist[k] = 0u;
-        if (MODEL == M_ELBM_MLP || p.stats) __syncthreads();
+            __syncthreads();
+        }
     }
 
     const bool active = x < p.nx && y < p.ny;
@@ -205,7 +201,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                 C heq[Q];
                 entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
                 const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
-                const AlphaOut ao = alpha_solve<L, C, MODEL == M_ELBM_MLP>(h, heq, double(m.rho), vsq, p, s_mlp);
+                const AlphaOut ao = alpha_solve<L, C, MODEL == M_ELBM_MLP>(h, heq, double(m.rho), vsq, p, p.mlp_wf);
                 const C ab = C(ao.alpha * p.beta);
 #pragma unroll
                 for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
