@@ -121,11 +121,6 @@ __device__ __forceinline__ void post_loc(int layout, int i, const Geo &g, int &s
     }
 }
 
-template <class St>
-__device__ __forceinline__ uint32_t sr_bits(const StepParams &p, uint32_t n, int i, uint32_t step_key) {
-    return hash32((n * 19u + uint32_t(i)) ^ step_key);
-}
-
 template <class L, class St, int MODEL, int LAYOUT, bool FLAGS>
 __global__ __launch_bounds__(512) void k_step(StepParams p) {
     using T = typename St::T;
@@ -211,12 +206,17 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                     if (!ao.converged) atomicAdd(&s_hist[NEWTON_BINS], 1u);
                 }
             }
-            uint32_t key = 0;
-            if constexpr (sizeof(T) == 2) key = hash32(p.seed ^ hash32(p.step + 0x9e3779b9u));
+            // stochastic rounding reads the top 16 bits of rnd: one draw serves two values
+            SrStream rs{0u};
+            uint32_t draw = 0;
+            if constexpr (St::stochastic) rs = sr_stream(n, hash32(p.seed ^ hash32(p.step + 0x9e3779b9u)));
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 uint32_t rnd = 0;
-                if constexpr (sizeof(T) == 2) rnd = sr_bits<St>(p, n, i, key);
+                if constexpr (St::stochastic) {
+                    if (i % 2 == 0) draw = rs.next();
+                    rnd = i % 2 == 0 ? draw : draw << 16;
+                }
                 out[i] = St::encode(o[i], C(L::w(i)), rnd);
             }
         }

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_step_vec(StepParams p) {
         for (int v = 0; v < VEC; v++) raw[i][v] = a[v];
     }
     uint32_t key = 0;
-    if constexpr (sizeof(T) == 2) key = hash32(p.seed ^ hash32(p.step + 0x9e3779b9u));
+    if constexpr (St::stochastic) key = hash32(p.seed ^ hash32(p.step + 0x9e3779b9u));
     T out[Q][VEC];
 #pragma unroll
     for (int v = 0; v < VEC; v++) {
@@ -82,10 +82,16 @@ __global__ __launch_bounds__(256) void k_step_vec(StepParams p) {
         for (int i = 0; i < Q; i++) h[i] = St::decode(raw[i][v], C(L::w(i)));
         if constexpr (MODEL == M_BGK) collide_bgk<L, C>(h, o, p);
         else collide_mrt<L, C>(h, o, p);
+        SrStream rs{0u};
+        uint32_t draw = 0;
+        if constexpr (St::stochastic) rs = sr_stream(own_n + v, key);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             uint32_t rnd = 0;
-            if constexpr (sizeof(T) == 2) rnd = sr_bits<St>(p, own_n + v, i, key);
+            if constexpr (St::stochastic) {
+                if (i % 2 == 0) draw = rs.next();
+                rnd = i % 2 == 0 ? draw : draw << 16;
+            }
             out[i][v] = St::encode(o[i], C(L::w(i)), rnd);
         }
     }

@@ -30,11 +30,28 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
     return x;
 }
 
+// Random bits for stochastic rounding: one hash per node and step seeds Marsaglia's
+// xorshift32 (shifts 13, 17, 5); each step gives the random bits of two stored values
+// (its high and its low half).  The seed is forced odd so the state is never 0.
+struct SrStream {
+    uint32_t s;
+    __device__ __forceinline__ uint32_t next() {
+        s ^= s << 13;
+        s ^= s >> 17;
+        s ^= s << 5;
+        return s;
+    }
+};
+__device__ __forceinline__ SrStream sr_stream(uint32_t node, uint32_t step_key) {
+    return SrStream{hash32(node ^ step_key) | 1u};
+}
+
 struct StF64 {
     using T = double;  // element in memory
     using C = double;  // compute type
     static constexpr int id = ST_F64;
     static constexpr bool shifted = false;
+    static constexpr bool stochastic = false;
     __device__ static __forceinline__ C decode(T v, C w) { return v - w; }
     __device__ static __forceinline__ T encode(C h, C w, uint32_t) { return h + w; }
 };
@@ -44,6 +61,7 @@ struct StF32 {
     using C = float;
     static constexpr int id = ST_F32;
     static constexpr bool shifted = false;
+    static constexpr bool stochastic = false;
     __device__ static __forceinline__ C decode(T v, C w) { return v - w; }
     __device__ static __forceinline__ T encode(C h, C w, uint32_t) { return h + w; }
 };
@@ -53,6 +71,7 @@ struct StF32S {
     using C = float;
     static constexpr int id = ST_F32S;
     static constexpr bool shifted = true;
+    static constexpr bool stochastic = false;
     __device__ static __forceinline__ C decode(T v, C) { return v; }
     __device__ static __forceinline__ T encode(C h, C, uint32_t) { return h; }
 };
@@ -66,6 +85,7 @@ struct StBF16S {
     using C = float;
     static constexpr int id = ST_BF16S;
     static constexpr bool shifted = true;
+    static constexpr bool stochastic = SR;
     __device__ static __forceinline__ C decode(T v, C) { return __uint_as_float(uint32_t(v) << 16); }
     __device__ static __forceinline__ T encode(C h, C, uint32_t rnd) {
         if constexpr (SR) {
@@ -78,37 +98,34 @@ struct StBF16S {
     }
 };
 
-// IEEE half kept as raw bits.  Stochastic rounding picks between the two halves that
-// bracket h with probability proportional to proximity.
+// IEEE half kept as raw bits.  Stochastic rounding rounds |h| up to the next half with
+// probability equal to the fraction of a half-ulp step it lies above the one below:
+//  - F16 normal range (|h| >= 2^-14): the half keeps 10 of FP32's 23 mantissa bits, so
+//    13 random bits are added below the kept ones and the rest truncated; a carry
+//    moves into the exponent as it should;
+//  - subnormal range: the spacing is 2^-24, so floor(|h| 2^24 + u) 2^-24, u from the
+//    top 16 random bits.
+// Either result is a half exactly, so the final conversion does not round.
 template <bool SR>
 struct StF16S {
     using T = uint16_t;
     using C = float;
     static constexpr int id = ST_F16S;
     static constexpr bool shifted = true;
+    static constexpr bool stochastic = SR;
     __device__ static __forceinline__ C decode(T v, C) {
         return static_cast<float>(__builtin_bit_cast(_Float16, v));
     }
     __device__ static __forceinline__ T encode(C h, C, uint32_t rnd) {
-        _Float16 r = static_cast<_Float16>(h);
-        uint16_t bits = __builtin_bit_cast(uint16_t, r);
         if constexpr (SR) {
-            float rf = static_cast<float>(r);
-            if (rf != h && (bits & 0x7c00u) != 0x7c00u) {
-                // neighbour of r on the side of h (sign-magnitude stepping)
-                bool up = (h > rf);
-                bool neg = (bits & 0x8000u) != 0;
-                uint16_t nb;
-                if ((bits & 0x7fffu) == 0) nb = up ? 0x0001u : 0x8001u;
-                else nb = (up != neg) ? uint16_t(bits + 1) : uint16_t(bits - 1);
-                float nf = static_cast<float>(__builtin_bit_cast(_Float16, nb));
-                // P(choose nb) = |h - rf| / |nf - rf|
-                float p = (h - rf) / (nf - rf);
-                float u = float(rnd >> 8) * (1.0f / 16777216.0f);
-                if (u < p) bits = nb;
-            }
+            const float a = fabsf(h);
+            const float up = __uint_as_float((__float_as_uint(a) + (rnd >> 19)) & ~0x1fffu);
+            const float sub = floorf(fmaf(a, 0x1p24f, float(rnd >> 16) * 0x1p-16f)) * 0x1p-24f;
+            const float q = a >= 0x1p-14f ? up : sub;
+            return __builtin_bit_cast(uint16_t, static_cast<_Float16>(copysignf(q, h)));
+        } else {
+            return __builtin_bit_cast(uint16_t, static_cast<_Float16>(h));
         }
-        return bits;
     }
 };
 
