@@ -99,18 +99,10 @@ size_t elem_size(int storage) {
 size_t compute_size(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 LaunchCfg node_cfg(const lbm_sim *s) {
-    int bx, by;
-#ifndef LBM_BLOCK_NODES
-#define LBM_BLOCK_NODES 256  // nodes per workgroup when whole rows fit (build-time tuning)
-#endif
-    if (s->nx % 64 == 0 && s->nx <= 512) {
-        bx = s->nx;
-        by = std::max(1, LBM_BLOCK_NODES / s->nx);
-    } else {
-        bx = std::min(256, ((s->nx + 63) / 64) * 64);
-        by = std::max(1, 256 / bx);
-    }
-    if (by > s->ny) by = std::max(1, s->ny);
+    // one x row, or a segment of at most 512 nodes of one, per workgroup: the step
+    // kernels take y and z from the workgroup index (scalar row and tile offsets)
+    const int bx = s->nx % 64 == 0 && s->nx <= 512 ? s->nx : std::min(256, ((s->nx + 63) / 64) * 64);
+    const int by = 1;
     LaunchCfg c;
     c.block = dim3(bx, by, 1);
     c.grid = dim3((s->nx + bx - 1) / bx, (s->ny + by - 1) / by, s->nz);

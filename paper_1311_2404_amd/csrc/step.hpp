@@ -18,6 +18,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#ifndef LBM_WIDE_ADDR
+#define LBM_WIDE_ADDR 0  // build variant: 1 gives 2-byte elements the per-lane address too
+#endif
+
 #include "collide.hpp"
 #include "elbm.hpp"
 #include "lattice.hpp"
@@ -68,10 +74,12 @@ struct Geo {
     __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const {
         return (z_of(dz) * ny + y_of(dy)) * nx + x_of(dx);
     }
-    __device__ __forceinline__ uint32_t pa(int dx, int dy, int dz) const {
+    // offset of the row of node (x, y + dy, z + dz) inside a population's block
+    __device__ __forceinline__ uint32_t row_off(int dy, int dz) const {
         const uint32_t yy = y_of(dy);
-        return (z_of(dz) * (ny >> tyl) + (yy >> tyl)) * rp + (yy & ((1u << tyl) - 1u)) * rpitch + x_of(dx);
+        return (z_of(dz) * (ny >> tyl) + (yy >> tyl)) * rp + (yy & ((1u << tyl) - 1u)) * rpitch;
     }
+    __device__ __forceinline__ uint32_t pa(int dx, int dy, int dz) const { return row_off(dy, dz) + x_of(dx); }
 };
 
 __device__ __forceinline__ Geo make_geo(int x, int y, int z, int nx, int ny, int nz, uint32_t rp,
@@ -92,6 +100,49 @@ __device__ __forceinline__ Geo make_geo(int x, int y, int z, int nx, int ny, int
     g.rpitch = rpitch;
     g.tyl = tyl;
     return g;
+}
+
+// Slot and neighbour offset of the physical population f_i(x) (where it is read) and of
+// the post-collision value f*_i(x) (where it is written).
+template <class L>
+__device__ __forceinline__ void canon_dir(int layout, int i, int &slot, int &dx, int &dy, int &dz) {
+    if (layout == LAYOUT_AA_EVEN) {
+        slot = i;
+        dx = dy = dz = 0;
+    } else {
+        slot = layout == LAYOUT_AB ? i : opp(i);
+        dx = -L::ex(i);
+        dy = -L::ey(i);
+        dz = -L::ez(i);
+    }
+}
+template <class L>
+__device__ __forceinline__ void post_dir(int layout, int i, int &slot, int &dx, int &dy, int &dz) {
+    slot = layout == LAYOUT_AA_EVEN ? opp(i) : i;
+    if (layout == LAYOUT_AA_ODD) {
+        dx = L::ex(i);
+        dy = L::ey(i);
+        dz = L::ez(i);
+    } else {
+        dx = dy = dz = 0;
+    }
+}
+
+// Address of population slot `slot` at node x + (dx, dy, dz) in a copy.  In the step
+// kernels y and z are the same for the whole workgroup, so the slot and row part is a
+// scalar base.  For 2-byte elements the x part is added as a 32-bit byte offset, which
+// lets the load take the scalar base and a 32-bit vector offset (no 64-bit address
+// arithmetic per lane), part of a +6% on the VALU-bound 16-bit steps.  For 4- and 8-byte
+// elements, which are bound by memory, the plain per-lane 64-bit address is ~1% faster.
+template <class T>
+__device__ __forceinline__ T *pop_addr(T *base, uint32_t S, int slot, const Geo &g, int dx, int dy, int dz) {
+    if constexpr (sizeof(T) == 2 && !LBM_WIDE_ADDR) {
+        T *row = base + (size_t(slot) * S + g.row_off(dy, dz));
+        using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+        return reinterpret_cast<T *>(reinterpret_cast<B *>(row) + g.x_of(dx) * uint32_t(sizeof(T)));
+    } else {
+        return base + (size_t(slot) * S + g.pa(dx, dy, dz));
+    }
 }
 
 // Where the physical population f_i(x) currently lives (slot, offset in the slot's block).
@@ -126,28 +177,15 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     using T = typename St::T;
     using C = typename St::C;
     constexpr int Q = L::Q;
-#if defined(LBM_XCD_REMAP)
-    // build variant: workgroups are dealt to the 8 XCDs round-robin by linear id; remap
-    // so that each XCD walks one contiguous slab of rows
-    uint32_t by = blockIdx.y, bz = blockIdx.z;
-    {
-        const uint32_t T8 = gridDim.y * gridDim.z, lin = blockIdx.y + gridDim.y * blockIdx.z;
-        if (gridDim.x == 1 && T8 % 8 == 0) {
-            const uint32_t r = (lin % 8) * (T8 / 8) + lin / 8;
-            by = r % gridDim.y;
-            bz = r / gridDim.y;
-        }
-    }
+    // Launched with one x row (or a segment of one) per workgroup: y and z come from the
+    // workgroup index, so all row and tile offsets are scalar; only x and x +- 1 vary.
+    // (Two 128-node rows per workgroup with y made wave-uniform by readfirstlane measured
+    // 2.5% faster on the 128-wide FP32 duct but 6% slower on every 16-bit step.)
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = by * blockDim.y + threadIdx.y;
-    const int z = bz;
-#else
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int y = blockIdx.y;
     const int z = blockIdx.z;
-#endif
-    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    const int nthr = blockDim.x * blockDim.y;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
 
     // ELBM only: the Newton-iteration histogram in LDS
     constexpr bool ELBM = MODEL == M_ELBM || MODEL == M_ELBM_MLP;
@@ -170,10 +208,9 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         T raw[Q];
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            int slot;
-            uint32_t nd;
-            canon_loc<L>(LAYOUT, i, g, slot, nd);
-            raw[i] = LBM_LOAD(src + size_t(slot) * S + nd, i);
+            int slot, dx, dy, dz;
+            canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+            raw[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
         }
         T out[Q];
         const bool wall = FLAGS && p.flags[n] == 1;
@@ -222,10 +259,9 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         }
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            int slot;
-            uint32_t nd;
-            post_loc<L>(LAYOUT, i, g, slot, nd);
-            LBM_STORE(dst + size_t(slot) * S + nd, out[i]);
+            int slot, dx, dy, dz;
+            post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+            LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), out[i]);
         }
     }
     if constexpr (ELBM) {
@@ -244,7 +280,7 @@ __global__ __launch_bounds__(512) void k_psi(StepParams p) {
     using T = typename St::T;
     using C = typename St::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int y = blockIdx.y;  // one row (segment) per workgroup
     const int z = blockIdx.z;
     if (x >= p.nx || y >= p.ny) return;
     const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
@@ -257,10 +293,9 @@ __global__ __launch_bounds__(512) void k_psi(StepParams p) {
         C r = C(0);
 #pragma unroll
         for (int i = 0; i < L::Q; i++) {
-            int slot;
-            uint32_t nd;
-            canon_loc<L>(LAYOUT, i, g, slot, nd);
-            r += St::decode(fc[size_t(slot) * p.S + nd], C(L::w(i)));
+            int slot, dx, dy, dz;
+            canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+            r += St::decode(*pop_addr(fc, p.S, slot, g, dx, dy, dz), C(L::w(i)));
         }
         const C rho = C(1) + r;
         psi[size_t(c) * p.N + n] = p.psi_mode == 1 ? C(1) - exp(-rho) : rho;
@@ -275,7 +310,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
     using C = typename St::C;
     constexpr int Q = L::Q;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int y = blockIdx.y;  // one row (segment) per workgroup
     const int z = blockIdx.z;
     if (x >= p.nx || y >= p.ny) return;
     const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
@@ -291,10 +326,9 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
     for (int c = 0; c < 2; c++) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            int slot;
-            uint32_t nd;
-            canon_loc<L>(LAYOUT, i, g, slot, nd);
-            h[c][i] = St::decode(LBM_LOAD(src + (size_t(c) * Q + slot) * S + nd, i), C(L::w(i)));
+            int slot, dx, dy, dz;
+            canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+            h[c][i] = St::decode(LBM_LOAD(pop_addr(src, S, c * Q + slot, g, dx, dy, dz), i), C(L::w(i)));
         }
         m[c] = moments<L, C>(h[c]);
     }
@@ -345,10 +379,9 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
         for (int i = 0; i < Q; i++) {
             uint32_t rnd = 0;
             if constexpr (sizeof(T) == 2) rnd = hash32(((n * 19u + uint32_t(i)) * 2u + uint32_t(c)) ^ key);
-            int slot;
-            uint32_t nd;
-            post_loc<L>(LAYOUT, i, g, slot, nd);
-            LBM_STORE(dst + (size_t(c) * Q + slot) * S + nd, St::encode(o[i], C(L::w(i)), rnd));
+            int slot, dx, dy, dz;
+            post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+            LBM_STORE(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), rnd));
         }
     }
 }
