@@ -45,6 +45,7 @@ struct lbm_sim {
     unsigned int *bad_d = nullptr;
     uint16_t *mlp_bf16 = nullptr;
     float *mlp_wf_d = nullptr;  // BF16 weights widened to FP32, then mu[6], isd[6]
+    uint32_t *mlp_lane_d = nullptr;  // per-lane MFMA operand table (64 x 44 words)
     float mlp_host[MLP_NTOTAL] = {0};  // FP32 weights + input normalisation (mu, isd)
     bool mlp_set = false;
     unsigned long long *stats_d = nullptr;
@@ -138,6 +139,7 @@ StepParams base_params(const lbm_sim *s) {
     p.alpha_init = s->alpha_init;
     p.mlp = s->mlp_set ? s->mlp_bf16 : nullptr;
     p.mlp_wf = s->mlp_wf_d;
+    p.mlp_lane = s->mlp_lane_d;
     p.stats = s->stats_on ? s->stats_d : nullptr;
     p.psi = s->psi_d;
     p.G = s->G;
@@ -571,7 +573,7 @@ void lbm_destroy(lbm_sim *s) {
     if (!s) return;
     if (s->ready || s->flags_d) (void)hipStreamSynchronize(s->stream);
     void *ptrs[] = {s->buf[0], s->buf[1], s->flags_d, s->psi_d, s->stage, s->macro_d, s->red_d, s->bad_d,
-                    s->mlp_bf16, s->mlp_wf_d, s->stats_d, s->mlp_w_d, s->mlp_m_d, s->mlp_v_d, s->mlp_g_d,
+                    s->mlp_bf16, s->mlp_wf_d, s->mlp_lane_d, s->stats_d, s->mlp_w_d, s->mlp_m_d, s->mlp_v_d, s->mlp_g_d,
                     s->mlp_norm_d, s->mlp_tnorm_d, s->mlp_part_d, s->mlp_acc_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -586,6 +588,7 @@ int mlp_alloc(lbm_sim *s, int64_t nbatch_max) {
     HIPCHK(s, hipSetDevice(s->device));
     if (!s->mlp_bf16) HIPCHK(s, hipMalloc(&s->mlp_bf16, sizeof(uint16_t) * MLP_NPARAM));
     if (!s->mlp_wf_d) HIPCHK(s, hipMalloc(&s->mlp_wf_d, sizeof(float) * MLP_NTOTAL));
+    if (!s->mlp_lane_d) HIPCHK(s, hipMalloc(&s->mlp_lane_d, sizeof(uint32_t) * 64 * MLP_LANE_WORDS));
     if (!s->mlp_w_d) {
         HIPCHK(s, hipMalloc(&s->mlp_w_d, sizeof(float) * MLP_NPARAM));
         HIPCHK(s, hipMalloc(&s->mlp_m_d, sizeof(float) * MLP_NPARAM));
@@ -609,7 +612,7 @@ int mlp_upload(lbm_sim *s) {
     HIPCHK(s, hipMemcpyAsync(s->mlp_w_d, s->mlp_host, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipMemcpyAsync(s->mlp_norm_d, s->mlp_host + MLP_NPARAM, sizeof(float) * MLP_NNORM,
                              hipMemcpyHostToDevice, s->stream));
-    HIPCHK(s, mlp_to_bf16(s->mlp_w_d, s->mlp_norm_d, s->mlp_bf16, s->mlp_wf_d, s->stream));
+    HIPCHK(s, mlp_to_bf16(s->mlp_w_d, s->mlp_norm_d, s->mlp_bf16, s->mlp_wf_d, s->mlp_lane_d, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     return LBM_OK;
 }
@@ -688,8 +691,8 @@ int lbm_mlp_forward(lbm_sim *s, const void *feat_dev, int64_t n, void *y_dev) {
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
     if (n < 0 || (n > 0 && (!feat_dev || !y_dev))) return fail(s, LBM_EINVAL, "bad count or NULL buffer");
     if (!s->mlp_set) return fail(s, LBM_ESTATE, "no MLP weights set");
-    HIPCHK(s, mlp_forward_bf16(s->mlp_wf_d, static_cast<const float *>(feat_dev), n, static_cast<float *>(y_dev),
-                               s->stream));
+    HIPCHK(s, mlp_forward_bf16(s->mlp_wf_d, s->mlp_lane_d, static_cast<const float *>(feat_dev), n,
+                               static_cast<float *>(y_dev), s->stream));
     return LBM_OK;
 }
 

@@ -116,7 +116,8 @@ struct MlpDatasetParams {
     int layout;
 };
 hipError_t launch_alpha_dataset(int lattice, int storage, const MlpDatasetParams &p, hipStream_t s);
-hipError_t mlp_forward_bf16(const float *wf, const float *x, int64_t n, float *y, hipStream_t s);
+hipError_t mlp_forward_bf16(const float *wf, const uint32_t *lane, const float *x, int64_t n, float *y,
+                            hipStream_t s);
 hipError_t mlp_loss_grad(const float *w, const float *x, const double *t, int64_t n, const float *mu,
                          const float *isd, float *partials, int nparts, float *grad, double *loss, hipStream_t s);
 hipError_t mlp_train_batch(const float *w, const float *x, const double *t, int64_t row0, int64_t nbatch,
@@ -126,7 +127,7 @@ hipError_t mlp_train_batch(const float *w, const float *x, const double *t, int6
 hipError_t mlp_resid_moments(const float *x, const double *t, int64_t n, double *acc, hipStream_t s);
 constexpr int MLP_TRAIN_BLOCK = 256;
 hipError_t mlp_adam(float *w, const float *grad, float *m, float *v, int t, float lr, hipStream_t s);
-hipError_t mlp_to_bf16(const float *w, const float *norm, uint16_t *wb, float *wf, hipStream_t s);
+hipError_t mlp_to_bf16(const float *w, const float *norm, uint16_t *wb, float *wf, uint32_t *lane, hipStream_t s);
 hipError_t mlp_moments(const float *x, int64_t n, double *acc, hipStream_t s);
 
 }  // namespace lbm

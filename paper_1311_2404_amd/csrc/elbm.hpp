@@ -75,8 +75,9 @@ __device__ __forceinline__ double recip(double f) {
     return fma(r, fma(-f, r, 1.0), r);
 }
 
+// the raw mass and momentum of heq - h (removed from D by alpha_D)
 template <class L, class C>
-__device__ __forceinline__ void alpha_prepare(const C *h, const C *heq, AlphaNode &s) {
+__device__ __forceinline__ void alpha_project(const C *h, const C *heq, AlphaNode &s) {
     s.dm = s.jx = s.jy = s.jz = 0.0;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
@@ -86,6 +87,48 @@ __device__ __forceinline__ void alpha_prepare(const C *h, const C *heq, AlphaNod
         if (L::ey(i)) s.jy += L::ey(i) * D;
         if (L::ez(i)) s.jz += L::ez(i) * D;
     }
+}
+
+// The six alpha features: log10(a2/rho), a3/a2, a4/a2, max(-d), max(d), |v|^2/c_s^2,
+// with a_k = sum_i f_i d_i^k.
+__device__ __forceinline__ void alpha_features_m(double a2, double a3, double a4, double mneg, double mpos,
+                                                 double rho, double vsq, float *x) {
+    x[0] = float(log10(a2 / rho));
+    x[1] = float(a3 / a2);
+    x[2] = float(a4 / a2);
+    x[3] = float(mneg);
+    x[4] = float(mpos);
+    x[5] = float(3.0 * vsq);
+}
+
+// Only what the MLP features need: a_2, a_3, a_4, max(-d), max(d) (and max |d| for the
+// short-cut), after alpha_project.  Lighter than alpha_prepare, so that the network can
+// run before the 16 moments exist.
+template <class L, class C>
+__device__ __forceinline__ double alpha_feature_pass(const C *h, const C *heq, const AlphaNode &s, double rho,
+                                                     double vsq, float *x) {
+    double a2 = 0.0, a3 = 0.0, a4 = 0.0, mneg = -1e300, mpos = -1e300, dmax = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const double D = alpha_D<L, C>(h, heq, s, i);
+        const double d = D * recip(L::w(i) + double(h[i]));
+        double t = D * d;
+        a2 += t;
+        t *= d;
+        a3 += t;
+        t *= d;
+        a4 += t;
+        mneg = fmax(mneg, -d);
+        mpos = fmax(mpos, d);
+        dmax = fmax(dmax, fabs(d));
+    }
+    alpha_features_m(a2, a3, a4, mneg, mpos, rho, vsq, x);
+    return dmax;
+}
+
+// max |d|, max(-d), max(d), a_max and the moments a_1..a_K, after alpha_project
+template <class L, class C>
+__device__ __forceinline__ void alpha_moments(const C *h, const C *heq, AlphaNode &s) {
     s.dmax = 0.0;
     s.mneg = s.mpos = -1e300;
 #pragma unroll
@@ -109,20 +152,33 @@ __device__ __forceinline__ void alpha_prepare(const C *h, const C *heq, AlphaNod
     s.amax = s.mneg > 0.0 ? 1.0 / s.mneg : INFINITY;
 }
 
+template <class L, class C>
+__device__ __forceinline__ void alpha_prepare(const C *h, const C *heq, AlphaNode &s) {
+    alpha_project<L, C>(h, heq, s);
+    alpha_moments<L, C>(h, heq, s);
+}
+
 // Newton with bisection safeguard on the logarithmic form of g, bracket [1, a_max).
-// Used where max |d_i| > ALPHA_SERIES_DMAX, which is rare in resolved flows, so d_i and
-// log1p(d_i) are recomputed each iteration rather than held in registers.
+// Used where max |d_i| > ALPHA_SERIES_DMAX, which is rare in resolved flows, so it is
+// written for few registers: f_i and d_i go to local arrays that a rolled loop reads (the
+// compiler keeps them in scratch memory, touched only when this path runs), instead of
+// 19 unrolled FP64 log1p pairs that would raise the register count of the whole kernel.
 template <class L, class C>
 __device__ __forceinline__ AlphaOut alpha_newton_log(const C *h, const C *heq, const AlphaNode &s, double a0,
-                                                  double tol, int maxit) {
+                                                     double tol, int maxit) {
+    double fl[L::Q], dl[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        fl[i] = L::w(i) + double(h[i]);
+        dl[i] = alpha_D<L, C>(h, heq, s, i) * recip(fl[i]);
+    }
     double lo = 1.0, hi = s.amax, a = a0;
     if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
     for (int k = 1; k <= maxit; k++) {
         double g = 0.0, dg = 0.0, gs = 0.0;
-#pragma unroll
+#pragma unroll 1
         for (int i = 0; i < L::Q; i++) {
-            const double f = L::w(i) + double(h[i]);
-            const double d = alpha_D<L, C>(h, heq, s, i) * recip(f);
+            const double f = fl[i], d = dl[i];
             const double l1 = log1p(d);
             const double ad = a * d;
             const double la = log1p(ad);
@@ -186,50 +242,92 @@ __device__ __forceinline__ float tanh_fast(float x) {
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
 
-// 6 -> 32 -> 32 -> 1 MLP, tanh hidden units, FP32 accumulation.  W holds the BF16
+// The alpha proposal network, 6 -> 32 -> 32 -> 1 with tanh hidden units, evaluated for
+// the 64 nodes of a wave at once on the matrix cores
+// (v_mfma_f32_32x32x16_bf16: BF16 operands, FP32 accumulation).  W holds the BF16
 // weights widened to FP32 (the same values) followed by the FP32 input normalisation:
 // W1[32][6], b1[32], W2[32][32], b2[32], w3[32], b3, mu[6], isd[6]; the network sees
-// (x - mu) * isd.  W is read with lane-uniform addresses, so the weights come through
-// scalar loads and feed the FMAs from scalar registers.  The output is added to the
-// series estimate of the root, 2 + (x1 - 2 x2)/3 = 2 + (a3 - 2 a4)/(3 a2), so the
-// network only carries the series' residual (which BF16 weights can represent to far
-// better absolute accuracy than alpha - 2).
-__device__ __forceinline__ float mlp_eval(const float *__restrict__ W, const float *xraw) {
-    float x[MLP_IN];
+// (x - mu) * isd.  Its output is added to the series estimate of the root,
+// 2 + (x1 - 2 x2)/3 = 2 + (a3 - 2 a4)/(3 a2), so it only carries the series' residual
+// (which BF16 weights can represent to far better absolute accuracy than alpha - 2).
+// Nodes run along N: the
+// wave's lanes 0-31 and 32-63 form two blocks of 32 nodes.  With that instruction lane l
+// supplies A[l%32][8(l/32) + t] and B[8(l/32) + t][l%32], t = 0..7, and gets
+// D[8(r/4) + 4(l/32) + r%4][l%32] in accumulator r = 0..15.
+//  - layer 1: Z1^T = [W1 | b1] [x; 1]: K = 7 used of 16, the features of the block's
+//    node in lanes 0-31 (the second block's come from lane l + 32), zeros above;
+//  - layer 2: Z2^T = W2 H1^T + b2: K = 32 as two chunks of 16, with the hidden index
+//    permuted so that chunk c of B is accumulators 8c..8c+7 of layer 1 in the same lane
+//    (no data moves between lanes); W2's columns are packed in the same order;
+//  - output: each lane sums w3 tanh(z2) over its 16 rows, and the two half-sums of a node
+//    (lanes l and l xor 32) are added.
+// The hidden activations and the normalised inputs enter the MFMA in BF16 (2^-9 relative
+// rounding); training runs in FP32 with tanhf.  MLP_LANE_WORDS words per lane, packed once when the weights change:
+// [0,4) layer-1 A (8 BF16), [4,12) layer-2 A, chunks 0 and 1, [12,28) b2 and [28,44) w3
+// of the lane's 16 accumulator rows.  Must be called by all 64 lanes of the wave.
+typedef __bf16 mlp_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float mlp_f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ mlp_bf16x8 mlp_words_bf16(uint4 w) {
+    return __builtin_bit_cast(mlp_bf16x8, w);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    return uint32_t(__builtin_bit_cast(uint16_t, static_cast<__bf16>(lo))) |
+           (uint32_t(__builtin_bit_cast(uint16_t, static_cast<__bf16>(hi))) << 16);
+}
+
+__device__ __forceinline__ float mlp_eval_wave(const uint32_t *__restrict__ lane_w, const float *__restrict__ W,
+                                               const float *xraw) {
+    const int l = __lane_id();
+    const uint4 *lw = reinterpret_cast<const uint4 *>(lane_w + l * MLP_LANE_WORDS);
+    // this lane's normalised features with the bias input, as 8 BF16
+    float xn[MLP_IN];
 #pragma unroll
-    for (int k = 0; k < MLP_IN; k++) x[k] = (xraw[k] - W[MLP_NPARAM + k]) * W[MLP_NPARAM + MLP_IN + k];
-    const float *W1 = W, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
-    const float *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
-    float h1[MLP_H];
+    for (int k = 0; k < MLP_IN; k++) xn[k] = (xraw[k] - W[MLP_NPARAM + k]) * W[MLP_NPARAM + MLP_IN + k];
+    const uint4 own = make_uint4(pack_bf16x2(xn[0], xn[1]), pack_bf16x2(xn[2], xn[3]), pack_bf16x2(xn[4], xn[5]),
+                                 pack_bf16x2(1.0f, 0.0f));
+    uint4 other;  // the features of lane l xor 32
+    other.x = uint32_t(__shfl_xor(int(own.x), 32, 64));
+    other.y = uint32_t(__shfl_xor(int(own.y), 32, 64));
+    other.z = uint32_t(__shfl_xor(int(own.z), 32, 64));
+    other.w = uint32_t(__shfl_xor(int(own.w), 32, 64));
+    const bool lo = l < 32;
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+    const mlp_bf16x8 a1 = mlp_words_bf16(lw[0]);
+    const mlp_bf16x8 a2c0 = mlp_words_bf16(lw[1]), a2c1 = mlp_words_bf16(lw[2]);
+    float part[2];
 #pragma unroll
-    for (int j = 0; j < MLP_H; j++) {
-        float s = b1[j];
+    for (int blk = 0; blk < 2; blk++) {
+        // block 0: nodes of lanes 0-31 (own features in lanes 0-31); block 1: lanes 32-63
+        const uint4 bw = lo ? (blk == 0 ? own : other) : zero;
+        mlp_f32x16 z1 = {};
+        z1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, mlp_words_bf16(bw), z1, 0, 0, 0);
+        uint4 h0, h1;  // tanh of accumulators 0-7 and 8-15 as BF16: layer 2's B chunks
+        h0.x = pack_bf16x2(tanh_fast(z1[0]), tanh_fast(z1[1]));
+        h0.y = pack_bf16x2(tanh_fast(z1[2]), tanh_fast(z1[3]));
+        h0.z = pack_bf16x2(tanh_fast(z1[4]), tanh_fast(z1[5]));
+        h0.w = pack_bf16x2(tanh_fast(z1[6]), tanh_fast(z1[7]));
+        h1.x = pack_bf16x2(tanh_fast(z1[8]), tanh_fast(z1[9]));
+        h1.y = pack_bf16x2(tanh_fast(z1[10]), tanh_fast(z1[11]));
+        h1.z = pack_bf16x2(tanh_fast(z1[12]), tanh_fast(z1[13]));
+        h1.w = pack_bf16x2(tanh_fast(z1[14]), tanh_fast(z1[15]));
+        mlp_f32x16 z2;
+        const float *b2 = reinterpret_cast<const float *>(lane_w + l * MLP_LANE_WORDS + 12);
 #pragma unroll
-        for (int k = 0; k < MLP_IN; k++) s = fmaf(W1[j * MLP_IN + k], x[k], s);
-        h1[j] = tanh_fast(s);
+        for (int r = 0; r < 16; r++) z2[r] = b2[r];
+        z2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2c0, mlp_words_bf16(h0), z2, 0, 0, 0);
+        z2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2c1, mlp_words_bf16(h1), z2, 0, 0, 0);
+        const float *w3 = reinterpret_cast<const float *>(lane_w + l * MLP_LANE_WORDS + 28);
+        float sum = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; r++) sum = fmaf(w3[r], tanh_fast(z2[r]), sum);
+        part[blk] = sum + __shfl_xor(sum, 32, 64);
     }
-    float y = b3[0];
-#pragma unroll 4
-    for (int j = 0; j < MLP_H; j++) {
-        float s = b2[j];
-#pragma unroll
-        for (int k = 0; k < MLP_H; k++) s = fmaf(W2[j * MLP_H + k], h1[k], s);
-        y = fmaf(w3[j], tanh_fast(s), y);
-    }
+    const float y = (lo ? part[0] : part[1]) + W[MLP_NPARAM - 1];
     return (2.0f + (xraw[1] - 2.0f * xraw[2]) * (1.0f / 3.0f)) + y;
 }
 
-// The six alpha features: log10(a2/rho), a3/a2, a4/a2, max(-d), max(d), |v|^2/c_s^2,
-// with a_k = sum_i f_i d_i^k.
-__device__ __forceinline__ void alpha_features_m(double a2, double a3, double a4, double mneg, double mpos,
-                                                 double rho, double vsq, float *x) {
-    x[0] = float(log10(a2 / rho));
-    x[1] = float(a3 / a2);
-    x[2] = float(a4 / a2);
-    x[3] = float(mneg);
-    x[4] = float(mpos);
-    x[5] = float(3.0 * vsq);
-}
 
 // Root on the form that fits the node: the power series where max |d_i| <= 0.1, else
 // the logarithms.
@@ -241,21 +339,16 @@ __device__ __forceinline__ AlphaOut alpha_root(const C *h, const C *heq, const A
 }
 
 // Full alpha for one node from its shifted populations h and shifted entropic
-// equilibrium heq: short-cut near equilibrium, first guess (2, the series estimate or,
-// in the kernel built with MLP, the network's proposal), then the FP64 root.
-template <class L, class C, bool MLP>
-__device__ __forceinline__ AlphaOut alpha_solve(const C *h, const C *heq, double rho, double vsq,
-                                                const StepParams &p, const float *__restrict__ mlp_w) {
+// equilibrium heq: short-cut near equilibrium, first guess (2 or the series estimate),
+// then the FP64 root.  (The MLP first guess has a kernel of its own, k_step_elbm_mlp.)
+template <class L, class C>
+__device__ __forceinline__ AlphaOut alpha_solve(const C *h, const C *heq, const StepParams &p) {
     AlphaNode s;
     alpha_prepare<L, C>(h, heq, s);
     if (s.dmax < ALPHA_SHORTCUT) return {2.0, 0, 1};
     double a0 = 2.0;
     if (p.alpha_init == 1) {
         a0 = 2.0 + (s.am[3] - 2.0 * s.am[4]) / (3.0 * s.am[2]);
-    } else if constexpr (MLP) {
-        float x[MLP_IN];
-        alpha_features_m(s.am[2], s.am[3], s.am[4], s.mneg, s.mpos, rho, vsq, x);
-        a0 = double(mlp_eval(mlp_w, x));
     }
     return alpha_root<L, C>(h, heq, s, a0, p.alpha_tol, p.alpha_maxit);
 }

@@ -72,13 +72,16 @@ __global__ __launch_bounds__(256) void k_alpha_dataset(MlpDatasetParams d) {
     d.valid[k] = ao.converged ? 1 : 0;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_forward_bf16(const float *__restrict__ wf, const float *x, int64_t n,
+// Every lane of a wave takes part in the wave-level evaluation; rows past n feed zeros
+// and store nothing.
+__global__ __launch_bounds__(256) void k_mlp_forward_bf16(const float *__restrict__ wf,
+                                                         const uint32_t *__restrict__ lane, const float *x, int64_t n,
                                                          float *y) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
     float xr[MLP_IN];
-    for (int j = 0; j < MLP_IN; j++) xr[j] = x[MLP_IN * r + j];
-    y[r] = mlp_eval(wf, xr);
+    for (int j = 0; j < MLP_IN; j++) xr[j] = r < n ? x[MLP_IN * r + j] : 0.0f;
+    const float v = mlp_eval_wave(lane, wf, xr);
+    if (r < n) y[r] = v;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -219,6 +222,31 @@ __global__ void k_to_bf16(const float *w, const float *norm, uint16_t *wb, float
     }
 }
 
+// The per-lane operand table of mlp_eval_wave (64 lanes x MLP_LANE_WORDS words) from the
+// BF16-valued FP32 weights.
+__global__ void k_mlp_lane_pack(const float *wf, uint32_t *lane) {
+    const int l = threadIdx.x;
+    if (l >= 64) return;
+    uint32_t *o = lane + l * MLP_LANE_WORDS;
+    const float *W1 = wf, *b1 = W1 + MLP_H * MLP_IN, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H, *w3 = b2 + MLP_H;
+    const int j = l % 32, q = l / 32;
+    float a[8];
+    // layer 1: [W1 row j | b1[j] | 0] in lanes 0-31 (K = 0..7), zeros for K = 8..15
+    for (int t = 0; t < 8; t++) a[t] = q == 0 ? (t < MLP_IN ? W1[j * MLP_IN + t] : (t == MLP_IN ? b1[j] : 0.0f)) : 0.0f;
+    for (int t = 0; t < 4; t++) o[t] = pack_bf16x2(a[2 * t], a[2 * t + 1]);
+    // layer 2, chunk c: W2[j][16c + 8(t/4) + 4q + t%4]
+    for (int c = 0; c < 2; c++) {
+        for (int t = 0; t < 8; t++) a[t] = W2[j * MLP_H + 16 * c + 8 * (t / 4) + 4 * q + (t % 4)];
+        for (int t = 0; t < 4; t++) o[4 + 4 * c + t] = pack_bf16x2(a[2 * t], a[2 * t + 1]);
+    }
+    // b2 and w3 of the accumulator rows 8(r/4) + 4q + r%4
+    for (int r = 0; r < 16; r++) {
+        const int row = 8 * (r / 4) + 4 * q + (r % 4);
+        o[12 + r] = __float_as_uint(b2[row]);
+        o[28 + r] = __float_as_uint(w3[row]);
+    }
+}
+
 // sums and sums of squares of the series residual alpha - (2 + (x1 - 2 x2)/3)
 __global__ __launch_bounds__(256) void k_resid_moments(const float *x, const double *t, int64_t n, double *partials) {
     __shared__ double s[2][256];
@@ -292,9 +320,10 @@ hipError_t launch_alpha_dataset(int lattice, int storage, const MlpDatasetParams
     });
 }
 
-hipError_t mlp_forward_bf16(const float *wf, const float *x, int64_t n, float *y, hipStream_t s) {
+hipError_t mlp_forward_bf16(const float *wf, const uint32_t *lane, const float *x, int64_t n, float *y,
+                            hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_mlp_forward_bf16<<<dim3(uint32_t((n + 255) / 256)), 256, 0, s>>>(wf, x, n, y);
+    k_mlp_forward_bf16<<<dim3(uint32_t((n + 255) / 256)), 256, 0, s>>>(wf, lane, x, n, y);
     return hipGetLastError();
 }
 
@@ -314,8 +343,9 @@ hipError_t mlp_adam(float *w, const float *grad, float *m, float *v, int t, floa
     return hipGetLastError();
 }
 
-hipError_t mlp_to_bf16(const float *w, const float *norm, uint16_t *wb, float *wf, hipStream_t s) {
+hipError_t mlp_to_bf16(const float *w, const float *norm, uint16_t *wb, float *wf, uint32_t *lane, hipStream_t s) {
     k_to_bf16<<<(MLP_NTOTAL + 255) / 256, 256, 0, s>>>(w, norm, wb, wf);
+    k_mlp_lane_pack<<<1, 64, 0, s>>>(wf, lane);
     return hipGetLastError();
 }
 

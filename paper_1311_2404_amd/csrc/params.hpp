@@ -5,15 +5,14 @@
 namespace lbm {
 
 enum Layout { LAYOUT_AB = 0, LAYOUT_AA_EVEN = 1, LAYOUT_AA_ODD = 2 };
-// M_ELBM_MLP: the entropic step built with the MLP first guess (a kernel of its own, so
-// that the network's registers do not weigh on the step without it)
-enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3, M_ELBM_MLP = 4 };
+enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3 };
 
 constexpr int MLP_IN = 6;
 constexpr int MLP_H = 32;
 constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 1313
 constexpr int MLP_NNORM = 2 * MLP_IN;                 // input normalisation mu[6], isd[6]
 constexpr int MLP_NTOTAL = MLP_NPARAM + MLP_NNORM;     // 1325
+constexpr int MLP_LANE_WORDS = 44;  // per-lane words of the wave-level (MFMA) network's operand table
 constexpr int NEWTON_BINS = 32;
 
 // Passed by value as the kernel argument of every step-like kernel.
@@ -40,6 +39,7 @@ struct StepParams {
     int alpha_init;             // 0: 2, 1: series, 2: MLP
     const uint16_t *mlp;        // bf16 MLP weights (alpha_init == 2)
     const float *mlp_wf;        // the same weights widened to FP32, then mu[6], isd[6]
+    const uint32_t *mlp_lane;   // per-lane MFMA operand table of the wave-level network
     unsigned long long *stats;  // [NEWTON_BINS] histogram + [1] non-converged, or nullptr
     // Shan-Chen
     const void *psi;            // psi[2][N] in compute precision

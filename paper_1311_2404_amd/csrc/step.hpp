@@ -188,7 +188,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     const int nthr = blockDim.x;
 
     // ELBM only: the Newton-iteration histogram in LDS
-    constexpr bool ELBM = MODEL == M_ELBM || MODEL == M_ELBM_MLP;
+    constexpr bool ELBM = MODEL == M_ELBM;
     __shared__ uint32_t s_hist[ELBM ? NEWTON_BINS + 1 : 1];
     if constexpr (ELBM) {
         if (p.stats) {
@@ -232,8 +232,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                 const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
                 C heq[Q];
                 entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
-                const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
-                const AlphaOut ao = alpha_solve<L, C, MODEL == M_ELBM_MLP>(h, heq, double(m.rho), vsq, p, p.mlp_wf);
+                const AlphaOut ao = alpha_solve<L, C>(h, heq, p);
                 const C ab = C(ao.alpha * p.beta);
 #pragma unroll
                 for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
@@ -270,6 +269,95 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             for (int k = tid; k < NEWTON_BINS + 1; k += nthr)
                 if (s_hist[k]) atomicAdd(&p.stats[k], (unsigned long long)s_hist[k]);
         }
+    }
+}
+
+// The entropic step with the MLP first guess.  The network runs on the matrix cores for
+// the 64 nodes of a wave at once (mlp_eval_wave), which needs every lane of the wave at
+// that point: so this kernel does not branch around it.  Lanes past the end of a row
+// work on a clamped node and store nothing; walls and nodes at the near-equilibrium
+// short-cut feed zero features and keep their own result.
+template <class L, class St, int LAYOUT, bool FLAGS>
+__global__ __launch_bounds__(512) void k_step_elbm_mlp(StepParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    constexpr int Q = L::Q;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;  // one x row (segment) per workgroup
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    __shared__ uint32_t s_hist[NEWTON_BINS + 1];
+    if (p.stats) {
+        for (int k = tid; k < NEWTON_BINS + 1; k += nthr) s_hist[k] = 0u;
+        __syncthreads();
+    }
+    const bool active = x < p.nx;
+    const Geo g = make_geo(active ? x : p.nx - 1, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+    const uint32_t n = g.at(0, 0, 0);
+    const uint32_t S = p.S;
+    const T *src = static_cast<const T *>(p.src);
+    T *dst = static_cast<T *>(p.dst);
+    T raw[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        int slot, dx, dy, dz;
+        canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+        raw[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
+    }
+    const bool wall = FLAGS && p.flags[n] == 1;
+    C h[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) h[i] = St::decode(raw[i], C(L::w(i)));
+    const Macro<C> m = moments<L, C>(h);
+    const C irho = C(1) / m.rho;
+    const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
+    C heq[Q];
+    entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
+    const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
+    // the features first, so that the 16 moments are not live across the network
+    AlphaNode an;
+    alpha_project<L, C>(h, heq, an);
+    float xf[MLP_IN];
+    const double dmax = alpha_feature_pass<L, C>(h, heq, an, double(m.rho), vsq, xf);
+    const bool solve = active && !wall && dmax >= ALPHA_SHORTCUT;
+#pragma unroll
+    for (int k = 0; k < MLP_IN; k++) xf[k] = solve ? xf[k] : 0.0f;
+    const double a0 = double(mlp_eval_wave(p.mlp_lane, p.mlp_wf, xf));  // all lanes of the wave
+    // the moments for every lane (kept out of the divergent branch, where the compiler's
+    // register allocation fails badly), the root where it is wanted
+    alpha_moments<L, C>(h, heq, an);
+    AlphaOut ao{2.0, 0, 1};
+    if (solve) ao = alpha_root<L, C>(h, heq, an, a0, p.alpha_tol, p.alpha_maxit);
+    T out[Q];
+    if (wall) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i] = raw[opp(i)];
+    } else {
+        const C ab = C(ao.alpha * p.beta);
+        C o[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
+        conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
+#pragma unroll
+        for (int i = 0; i < Q; i++) out[i] = St::encode(o[i], C(L::w(i)), 0u);
+        if (p.stats && active) {
+            atomicAdd(&s_hist[ao.iters < NEWTON_BINS ? ao.iters : NEWTON_BINS - 1], 1u);
+            if (!ao.converged) atomicAdd(&s_hist[NEWTON_BINS], 1u);
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            int slot, dx, dy, dz;
+            post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+            LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), out[i]);
+        }
+    }
+    if (p.stats) {
+        __syncthreads();
+        for (int k = tid; k < NEWTON_BINS + 1; k += nthr)
+            if (s_hist[k]) atomicAdd(&p.stats[k], (unsigned long long)s_hist[k]);
     }
 }
 

@@ -13,8 +13,8 @@ hipError_t launch_step_elbm(int lattice, int storage, int layout, bool flags, co
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
                 if (p.alpha_init == 2 && p.mlp) {
-                    if (flags) k_step<L, St, M_ELBM_MLP, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
-                    else k_step<L, St, M_ELBM_MLP, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                    if (flags) k_step_elbm_mlp<L, St, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
+                    else k_step_elbm_mlp<L, St, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
                 } else {
                     if (flags) k_step<L, St, M_ELBM, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
                     else k_step<L, St, M_ELBM, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
