@@ -135,12 +135,14 @@ int lbm_diag(lbm_sim *sim, double out[8]);
  * block); reset != 0 clears the counters.  Synchronises when reading. */
 int lbm_elbm_stats(lbm_sim *sim, int enable, int reset, int64_t *hist, int nbins, int64_t *nonconv);
 
-/* ELBM alpha MLP (6 -> 32 -> 32 -> 1, tanh hidden units, output 2 + linear), the learned
- * first guess of the alpha Newton solve.  params[n]: n = 1313 weights W1[32][6], b1[32],
- * W2[32][32], b2[32], w3[32], b3 (inputs used as given), or n = 1325 with the input
- * normalisation mu[6], isd[6] appended (the network sees (x - mu) * isd).  FP32 in; the
- * library keeps the weights as BF16 for inference (FP32 accumulation, FP32 normalisation)
- * and an FP32 master copy for training.  get returns the master copy (n = 1313 or 1325). */
+/* ELBM alpha MLP (6 -> 32 -> 32 -> 1, tanh hidden units, linear output), the learned
+ * first guess of the alpha Newton solve: the proposal is the series estimate
+ * 2 + (x1 - 2 x2)/3 of the root plus the network's output, so the network carries only
+ * the series' residual.  params[n]: n = 1313 weights W1[32][6], b1[32], W2[32][32],
+ * b2[32], w3[32], b3 (inputs used as given), or n = 1325 with the input normalisation
+ * mu[6], isd[6] appended (the network sees (x - mu) * isd).  FP32 in; the library keeps
+ * the weights as BF16 for inference and an FP32 master copy for training.  get returns
+ * the master copy (n = 1313 or 1325). */
 int lbm_mlp_set_weights(lbm_sim *sim, const float *params, int n);
 int lbm_mlp_get_weights(lbm_sim *sim, float *params, int n);
 
@@ -156,8 +158,11 @@ int lbm_alpha_dataset(lbm_sim *sim, int64_t n, uint64_t seed, void *feat_dev, vo
  * and Adam (beta1 0.9, beta2 0.999, eps 1e-8), FP32 master weights starting from the
  * current ones (set them first: LBM_ESTATE otherwise).  The input normalisation is
  * refitted on the data (mean, 1/std) and the current weights are carried over to it
- * exactly.  Minibatches of `batch` rows of a seeded permutation each epoch.
- * loss_out[epochs] (host, may be NULL) receives the mean training loss per epoch. */
+ * exactly; the target, alpha minus the series estimate, is standardised the same way
+ * (the output layer is carried into and out of those units exactly), so a new network
+ * should start with a zero output layer.  Minibatches of `batch` rows of a seeded
+ * permutation each epoch.  loss_out[epochs] (host, may be NULL) receives the mean
+ * training loss per epoch, in alpha units. */
 int lbm_mlp_train(lbm_sim *sim, const void *feat_dev, const void *alpha_dev, int64_t n,
                   int epochs, int batch, float lr, uint64_t seed, float *loss_out);
 
@@ -167,8 +172,10 @@ int lbm_mlp_train(lbm_sim *sim, const void *feat_dev, const void *alpha_dev, int
 int lbm_mlp_loss_grad(lbm_sim *sim, const void *feat_dev, const void *alpha_dev, int64_t n,
                       double *loss, float *grad);
 
-/* MLP inference with the BF16 inference weights and FP32 normalisation: y_dev[n] (FP32)
- * from feat_dev[n][6]. */
+/* MLP inference as in the entropic step: y_dev[n] (FP32 proposal) from feat_dev[n][6].
+ * FP32 normalisation; the 64 rows of a wave go through the matrix cores together, with
+ * the BF16 weights, the normalised inputs and the hidden activations as BF16 operands
+ * and FP32 accumulation. */
 int lbm_mlp_forward(lbm_sim *sim, const void *feat_dev, int64_t n, void *y_dev);
 
 /* Steps taken since the last init / set_f. */
