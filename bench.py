@@ -280,10 +280,18 @@ def main():
         t0 = time.perf_counter()
         o.run(args.cpu_steps)
         dt = time.perf_counter() - t0
-        cpu = {"value": round(N * args.cpu_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+        cores = oracle.threads()
+        # the same oracle on one thread, over a shorter sample
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        o.run(1)
+        dt1 = time.perf_counter() - t1
+        oracle.set_threads(cores)
+        cpu = {"value": round(N * args.cpu_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
                "kind": "oracle",
                "sample": "FP64 oracle, the same 256^3 D3Q19 BGK Taylor-Green state, %d steps (%.1f s)"
-                         % (args.cpu_steps, dt)}
+                         % (args.cpu_steps, dt),
+               "single_thread_mlups": round(N / dt1 / 1e6, 3)}
 
     tag = "d3q19_bgk_f32_%s_%d" % (args.layout, n)
     traffic = stored_traffic(tag, N)

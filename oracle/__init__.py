@@ -57,6 +57,8 @@ def lib():
         ip = C.POINTER(C.c_int)
         P = C.POINTER(Params)
         L.orc_q.argtypes = [C.c_int]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
         L.orc_tables.argtypes = [C.c_int, ip, dp, ip]
         L.orc_feq.argtypes = [C.c_int, C.c_double, dp, dp]
         L.orc_feq_entropic.argtypes = [C.c_int, C.c_double, dp, dp]
@@ -251,3 +253,8 @@ class Oracle:
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))

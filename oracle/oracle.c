@@ -105,6 +105,15 @@ int orc_threads(void) {
 #endif
 }
 
+/* Threads for the following parallel loops (n >= 1); the arithmetic does not depend on it. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---- equilibria ----------------------------------------------------------- */
 
 /* Second-order polynomial equilibrium (equilibrium equation of section 2). */

@@ -70,6 +70,7 @@ int orc_init_eq(const orc_params *P, const double *rho, const double *u, const d
 int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc_stats *st);
 int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double *rho, double *u);
 int orc_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
