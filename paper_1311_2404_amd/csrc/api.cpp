@@ -100,10 +100,14 @@ size_t elem_size(int storage) {
 size_t compute_size(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 LaunchCfg node_cfg(const lbm_sim *s) {
-    // one x row, or a segment of at most 512 nodes of one, per workgroup: the step
-    // kernels take y and z from the workgroup index (scalar row and tile offsets)
+    // x rows (or segments of at most 512 nodes) of whole waves per workgroup, so that y and
+    // z are wave-uniform in the step kernels (scalar row and tile offsets).  One row per
+    // workgroup, except BGK and MRT with 4- or 8-byte elements on rows of at most 128 nodes,
+    // which take 256 / bx rows (their kernels read y per wave).
     const int bx = s->nx % 64 == 0 && s->nx <= 512 ? s->nx : std::min(256, ((s->nx + 63) / 64) * 64);
-    const int by = 1;
+    int by = 1;
+    if ((s->model == LBM_BGK || s->model == LBM_MRT) && elem_size(s->storage) >= 4 && bx <= 128)
+        by = std::min(256 / bx, std::max(1, s->ny));
     LaunchCfg c;
     c.block = dim3(bx, by, 1);
     c.grid = dim3((s->nx + bx - 1) / bx, (s->ny + by - 1) / by, s->nz);

@@ -177,15 +177,20 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     using T = typename St::T;
     using C = typename St::C;
     constexpr int Q = L::Q;
-    // Launched with one x row (or a segment of one) per workgroup: y and z come from the
-    // workgroup index, so all row and tile offsets are scalar; only x and x +- 1 vary.
-    // (Two 128-node rows per workgroup with y made wave-uniform by readfirstlane measured
-    // 2.5% faster on the 128-wide FP32 duct but 6% slower on every 16-bit step.)
+    // Rows of the workgroup are whole waves, so y and z are the same for every lane of a
+    // wave: all row and tile offsets are scalar; only x and x +- 1 vary.  BGK and MRT with
+    // 4- and 8-byte elements take two 128-node rows per workgroup where rows are that
+    // short (y made wave-uniform by readfirstlane; +2.5% on the 128-wide FP32 duct); every
+    // other step takes one row per workgroup and y from the workgroup index (the
+    // readfirstlane form measured 6% slower on the 16-bit steps).
+    constexpr bool MULTI_ROW = sizeof(T) >= 4 && (MODEL == M_BGK || MODEL == M_MRT);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
+    int y;
+    if constexpr (MULTI_ROW) y = blockIdx.y * blockDim.y + __builtin_amdgcn_readfirstlane(threadIdx.y);
+    else y = blockIdx.y;
     const int z = blockIdx.z;
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
+    const int tid = MULTI_ROW ? threadIdx.y * blockDim.x + threadIdx.x : threadIdx.x;
+    const int nthr = MULTI_ROW ? blockDim.x * blockDim.y : blockDim.x;
 
     // ELBM only: the Newton-iteration histogram in LDS
     constexpr bool ELBM = MODEL == M_ELBM;
