@@ -125,7 +125,7 @@ hipError_t mlp_train_batch(const float *w, const float *x, const double *t, int6
                            double tinv, float *partials, float *grad, double *loss_acc, hipStream_t s);
 // acc[0] = sum, acc[1] = sum of squares of alpha - series base; acc[2 .. 2 + 128) scratch
 hipError_t mlp_resid_moments(const float *x, const double *t, int64_t n, double *acc, hipStream_t s);
-constexpr int MLP_TRAIN_BLOCK = 256;
+constexpr int MLP_TRAIN_BLOCK = 64;  // one wave per training block
 hipError_t mlp_adam(float *w, const float *grad, float *m, float *v, int t, float lr, hipStream_t s);
 hipError_t mlp_to_bf16(const float *w, const float *norm, uint16_t *wb, float *wf, uint32_t *lane, hipStream_t s);
 hipError_t mlp_moments(const float *x, int64_t n, double *acc, hipStream_t s);

@@ -90,24 +90,34 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-constexpr int TB = MLP_TRAIN_BLOCK;  // threads per training block
-constexpr int TW = TB / 64;        // waves per block
+constexpr int TB = MLP_TRAIN_BLOCK;  // samples (and threads: one wave) per training block
+static_assert(TB == 64, "one wave per training block");
 
-// One block = up to TB samples.  Sample r of the batch is row idx(r) of the data,
-// idx(r) = (a r + b) mod n_all when a permutation is given (a coprime to n_all), the
-// identity otherwise.  Inputs are normalised as (x - mu) * isd.  Writes the block's
-// gradient (sum over its samples of d loss / d w, loss = mean over the batch) and
-// squared-error sum into partials[block][MLP_NPARAM + 1].
+// Columns of the per-sample backward rows kept in LDS: A = [d1(32), d2(32), dy],
+// B = [x(6), h1(32), h2(32), 1].  The gradient of weight p is sum_s A[s][ia] B[s][ib].
+constexpr int GA_D1 = 0, GA_D2 = 32, GA_DY = 64, GA_W = 65;
+constexpr int GB_X = 0, GB_H1 = 6, GB_H2 = 38, GB_ONE = 70, GB_W = 72;
+
+// One block = one wave = up to 64 samples.  Sample r of the batch is row idx(r) of the
+// data, idx(r) = (a r + b) mod n_all when a permutation is given (a coprime to n_all),
+// the identity otherwise.  Inputs are normalised as (x - mu) * isd.  Each lane runs the
+// forward and backward pass of its sample and leaves the vectors the weight gradients
+// need in LDS; the lanes then sum them over the block's samples in a fixed order (W2's
+// 32 x 32 gradient as 4 x 4 tiles per lane, the other 289 weights one at a time), so a
+// training run is deterministic.  Writes the block's gradient (sum over its samples of
+// d loss / d w, loss = mean over the batch) and squared-error sum into
+// partials[block][MLP_NPARAM + 1].
 __global__ __launch_bounds__(TB) void k_mlp_grad(const float *w, const float *xall, const double *tall,
                                                  int64_t row0, int64_t nbatch, int64_t n_all, uint64_t pa,
                                                  uint64_t pb, const float *mu, const float *isd, double tmean,
                                                  double tinv, float *partials) {
     __shared__ float s_w[MLP_NPARAM];
-    __shared__ float s_g[TW][MLP_NPARAM + 1];
+    __shared__ float sA[TB][GA_W + 1];
+    __shared__ float sB[TB][GB_W + 1];
     for (int k = threadIdx.x; k < MLP_NPARAM; k += TB) s_w[k] = w[k];
     __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t r = int64_t(blockIdx.x) * TB + threadIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t r = int64_t(blockIdx.x) * TB + lane;
     const bool live = r < nbatch;
     float x[MLP_IN] = {0, 0, 0, 0, 0, 0};
     float base = 2.0f, t = 2.0f;
@@ -141,51 +151,74 @@ __global__ __launch_bounds__(TB) void k_mlp_grad(const float *w, const float *xa
     }
     const float err = live ? (yv - t) : 0.0f;
     const float dy = live ? 2.0f * err / float(nbatch) : 0.0f;
-    float *gW1 = s_g[wv], *gb1 = gW1 + MLP_H * MLP_IN, *gW2 = gb1 + MLP_H, *gb2 = gW2 + MLP_H * MLP_H;
-    float *gw3 = gb2 + MLP_H, *gb3 = gw3 + MLP_H;
-    {
-        const float v = wave_sum(dy);
-        if (lane == 0) gb3[0] = v;
-        const float e2 = wave_sum(err * err);
-        if (lane == 0) s_g[wv][MLP_NPARAM] = e2;
-    }
+    // backward vectors of this sample into LDS (zeros for rows past the batch)
+    float *A = sA[lane], *B = sB[lane];
+    A[GA_DY] = dy;
+#pragma unroll
+    for (int k = 0; k < MLP_IN; k++) B[GB_X + k] = x[k];
+    B[GB_ONE] = 1.0f;
     float d2[MLP_H];
 #pragma unroll
     for (int j = 0; j < MLP_H; j++) {
-        const float v = wave_sum(dy * h2[j]);
-        if (lane == 0) gw3[j] = v;
         d2[j] = dy * w3[j] * (1.0f - h2[j] * h2[j]);
-    }
-#pragma unroll 2
-    for (int j = 0; j < MLP_H; j++) {
-        const float vb = wave_sum(d2[j]);
-        if (lane == 0) gb2[j] = vb;
-#pragma unroll
-        for (int k = 0; k < MLP_H; k++) {
-            const float v = wave_sum(d2[j] * h1[k]);
-            if (lane == 0) gW2[j * MLP_H + k] = v;
-        }
+        A[GA_D2 + j] = d2[j];
+        B[GB_H1 + j] = h1[j];
+        B[GB_H2 + j] = h2[j];
     }
 #pragma unroll 2
     for (int k = 0; k < MLP_H; k++) {
         float s = 0.0f;
 #pragma unroll
         for (int j = 0; j < MLP_H; j++) s = fmaf(W2[j * MLP_H + k], d2[j], s);
-        const float d1 = s * (1.0f - h1[k] * h1[k]);
-        const float vb = wave_sum(d1);
-        if (lane == 0) gb1[k] = vb;
-#pragma unroll
-        for (int m = 0; m < MLP_IN; m++) {
-            const float v = wave_sum(d1 * x[m]);
-            if (lane == 0) gW1[k * MLP_IN + m] = v;
-        }
+        A[GA_D1 + k] = s * (1.0f - h1[k] * h1[k]);
     }
+    const float e2 = wave_sum(err * err);
     __syncthreads();
-    for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += TB) {
-        float acc = 0.0f;
-        for (int q = 0; q < TW; q++) acc += s_g[q][k];
-        partials[size_t(blockIdx.x) * (MLP_NPARAM + 1) + k] = acc;
+    float *part = partials + size_t(blockIdx.x) * (MLP_NPARAM + 1);
+    // W2: lane owns rows j0..j0+3 and columns k0..k0+3
+    {
+        const int j0 = 4 * (lane >> 3), k0 = 4 * (lane & 7);
+        float acc[4][4] = {};
+        for (int smp = 0; smp < TB; smp++) {
+            float av[4], bv[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                av[q] = sA[smp][GA_D2 + j0 + q];
+                bv[q] = sB[smp][GB_H1 + k0 + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) acc[q][v] = fmaf(av[q], bv[v], acc[q][v]);
+        }
+        float *gW2 = part + MLP_H * MLP_IN + MLP_H;
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) gW2[(j0 + q) * MLP_H + k0 + v] = acc[q][v];
     }
+    // the other weights: W1, b1 (d1 against x and 1), b2 (d2 against 1), w3, b3 (dy
+    // against h2 and 1)
+    constexpr int NW1 = MLP_H * MLP_IN, NREST = NW1 + MLP_H + 2 * MLP_H + 1;  // 289
+    static_assert(NREST + MLP_H * MLP_H == MLP_NPARAM, "every weight but W2's once");
+    for (int q = lane; q < NREST; q += TB) {
+        int p, ia, ib;
+        if (q < NW1) {
+            p = q; ia = GA_D1 + q / MLP_IN; ib = GB_X + q % MLP_IN;                      // W1[j][k]
+        } else if (q < NW1 + MLP_H) {
+            p = q; ia = GA_D1 + (q - NW1); ib = GB_ONE;                                  // b1[j]
+        } else {
+            const int u = q - NW1 - MLP_H;                                               // b2, w3, b3
+            p = NW1 + MLP_H + MLP_H * MLP_H + u;
+            if (u < MLP_H) { ia = GA_D2 + u; ib = GB_ONE; }
+            else if (u < 2 * MLP_H) { ia = GA_DY; ib = GB_H2 + (u - MLP_H); }
+            else { ia = GA_DY; ib = GB_ONE; }
+        }
+        float acc = 0.0f;
+        for (int smp = 0; smp < TB; smp++) acc = fmaf(sA[smp][ia], sB[smp][ib], acc);
+        part[p] = acc;
+    }
+    if (lane == 0) part[MLP_NPARAM] = e2;
 }
 
 __global__ void k_mlp_reduce(const float *partials, int nparts, float *grad, double *loss_acc, int64_t nbatch) {

@@ -107,8 +107,10 @@ def test_loss_and_gradient_match_oracle():
     P.lbm_mlp_set_weights(s.h, p)
     loss, g = P.lbm_mlp_loss_grad(s.h, dev(x, torch.float32), dev(t, torch.float64), n)
     lo, go = oracle.mlp_loss_grad(p.astype(np.float64), x.astype(np.float64), t)
-    assert abs(loss - lo) <= 1e-5 * lo
-    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+    # FP32 forward and backward per sample, FP32 sums over a block's 64 samples in a fixed
+    # order, FP64 over blocks: a few 1e-7 relative; 3 000 rows span 47 blocks and a ragged tail
+    assert abs(loss - lo) <= 1e-6 * lo
+    assert np.linalg.norm(g - go) <= 5e-6 * np.linalg.norm(go)
     s.close()
 
 
