@@ -97,14 +97,17 @@ __device__ __forceinline__ void conserve(C *o, C drho, C jx, C jy, C jz) {
 }
 
 // ---------------------------------------------------------------------------- BGK
-template <class L, class C>
-__device__ __forceinline__ void collide_bgk(const C *h, C *o, const StepParams &p) {
+// FORCE is the wave-uniform has_force flag made a template argument, so a step without
+// a body force carries no forcing arithmetic (the compiler would otherwise evaluate the
+// forcing term and select it away).
+template <class L, class C, bool FORCE>
+__device__ __forceinline__ void collide_bgk_body(const C *h, C *o, const StepParams &p) {
     const Macro<C> m = moments<L, C>(h);
     const C omega = C(p.omega);
     const C irho = C(1) / m.rho;
     C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
     C Fx = C(0), Fy = C(0), Fz = C(0);
-    if (p.has_force) {
+    if constexpr (FORCE) {
         const C gx = C(p.g[0]), gy = C(p.g[1]), gz = C(L::D == 3 ? p.g[2] : 0.0);
         vx += C(0.5) * gx;
         vy += C(0.5) * gy;
@@ -114,21 +117,28 @@ __device__ __forceinline__ void collide_bgk(const C *h, C *o, const StepParams &
         Fz = m.rho * gz;
     }
     const C usq15 = C(1.5) * (vx * vx + vy * vy + vz * vz);
-    const C pre = C(1) - C(0.5) * omega;
-    const C vF = vx * Fx + vy * Fy + vz * Fz;
+    [[maybe_unused]] const C pre = C(1) - C(0.5) * omega;
+    [[maybe_unused]] const C vF = vx * Fx + vy * Fy + vz * Fz;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
         const C w = C(L::w(i));
         const C eu = C(L::ex(i)) * vx + C(L::ey(i)) * vy + C(L::ez(i)) * vz;
         const C heq = w * (m.drho + m.rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
         C r = h[i] + omega * (heq - h[i]);
-        if (p.has_force) {
+        if constexpr (FORCE) {
             const C eF = C(L::ex(i)) * Fx + C(L::ey(i)) * Fy + C(L::ez(i)) * Fz;
             r += pre * w * (C(3) * (eF - vF) + C(9) * eu * eF);
         }
         o[i] = r;
     }
-    conserve<L, C>(o, m.drho, m.jx + Fx, m.jy + Fy, m.jz + Fz);
+    if constexpr (FORCE) conserve<L, C>(o, m.drho, m.jx + Fx, m.jy + Fy, m.jz + Fz);
+    else conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
+}
+
+template <class L, class C>
+__device__ __forceinline__ void collide_bgk(const C *h, C *o, const StepParams &p) {
+    if (p.has_force) collide_bgk_body<L, C, true>(h, o, p);
+    else collide_bgk_body<L, C, false>(h, o, p);
 }
 
 // ---------------------------------------------------------------------------- MRT
@@ -136,7 +146,7 @@ __device__ __forceinline__ void collide_bgk(const C *h, C *o, const StepParams &
 // (5q-9)ey, ez, (5q-9)ez, 3ex^2-q, (3q-5)(3ex^2-q), ey^2-ez^2, (3q-5)(ey^2-ez^2),
 // exey, eyez, exez, (ey^2-ez^2)ex, (ez^2-ex^2)ey, (ex^2-ey^2)ez; squared norms
 // 19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8.
-template <class C>
+template <class C, bool FORCE>
 __device__ __forceinline__ void collide_mrt_d3q19(const C *h, C *o, const StepParams &p) {
     // pair sums and differences (opposite directions are adjacent)
     const C s1 = h[1] + h[2], d1 = h[1] - h[2];
@@ -177,7 +187,7 @@ __device__ __forceinline__ void collide_mrt_d3q19(const C *h, C *o, const StepPa
     const C irho = C(1) / rho;
     C vx = jx * irho, vy = jy * irho, vz = jz * irho;
     C Fx = C(0), Fy = C(0), Fz = C(0);
-    if (p.has_force) {
+    if constexpr (FORCE) {
         vx += C(0.5) * C(p.g[0]);
         vy += C(0.5) * C(p.g[1]);
         vz += C(0.5) * C(p.g[2]);
@@ -222,14 +232,18 @@ __device__ __forceinline__ void collide_mrt_d3q19(const C *h, C *o, const StepPa
                       C(72), C(12), C(24), C(4), C(4), C(4), C(8), C(8), C(8)};
     C a[19];
     a[0] = drho / n2[0];
-    a[3] = (jx + Fx) / n2[3];
-    a[5] = (jy + Fy) / n2[5];
-    a[7] = (jz + Fz) / n2[7];
+    // momentum after the force's full step (no add of a zero force: -0 + 0 is +0)
+    const C Jx = FORCE ? jx + Fx : jx, Jy = FORCE ? jy + Fy : jy, Jz = FORCE ? jz + Fz : jz;
+    a[3] = Jx / n2[3];
+    a[5] = Jy / n2[5];
+    a[7] = Jz / n2[7];
 #pragma unroll
     for (int k = 1; k < 19; k++) {
         if (k == 3 || k == 5 || k == 7) continue;
         const C sk = C(p.s[k]);
-        a[k] = (m[k] - sk * (m[k] - meq[k]) + (C(1) - C(0.5) * sk) * mf[k]) * (C(1) / n2[k]);
+        C r = m[k] - sk * (m[k] - meq[k]);
+        if constexpr (FORCE) r += (C(1) - C(0.5) * sk) * mf[k];
+        a[k] = r * (C(1) / n2[k]);
     }
     // inverse transform M^T a, even/odd parts per opposite pair
     o[0] = a[0] - C(30) * a[1] + C(12) * a[2];
@@ -261,12 +275,12 @@ __device__ __forceinline__ void collide_mrt_d3q19(const C *h, C *o, const StepPa
     o[15] = E + O; o[16] = E - O;
     E = Eyz - a[14]; O = oy - oz + a[17] + a[18];
     o[17] = E + O; o[18] = E - O;
-    conserve<D3Q19, C>(o, drho, jx + Fx, jy + Fy, jz + Fz);
+    conserve<D3Q19, C>(o, drho, Jx, Jy, Jz);
 }
 
 // D2Q9 basis rows: 1, 3q-4, (9q^2-21q+8)/2, ex, (3q-5)ex, ey, (3q-5)ey, ex^2-ey^2, exey;
 // squared norms 9, 36, 36, 6, 12, 6, 12, 4, 4.
-template <class C>
+template <class C, bool FORCE>
 __device__ __forceinline__ void collide_mrt_d2q9(const C *h, C *o, const StepParams &p) {
     const C s1 = h[1] + h[2], d1 = h[1] - h[2];
     const C s3 = h[3] + h[4], d3 = h[3] - h[4];
@@ -286,7 +300,7 @@ __device__ __forceinline__ void collide_mrt_d2q9(const C *h, C *o, const StepPar
     const C rho = C(1) + drho;
     const C irho = C(1) / rho;
     C vx = jx * irho, vy = jy * irho, Fx = C(0), Fy = C(0);
-    if (p.has_force) {
+    if constexpr (FORCE) {
         vx += C(0.5) * C(p.g[0]);
         vy += C(0.5) * C(p.g[1]);
         Fx = rho * C(p.g[0]);
@@ -309,13 +323,16 @@ __device__ __forceinline__ void collide_mrt_d2q9(const C *h, C *o, const StepPar
     const C n2[9] = {C(9), C(36), C(36), C(6), C(12), C(6), C(12), C(4), C(4)};
     C a[9];
     a[0] = drho / n2[0];
-    a[3] = (jx + Fx) / n2[3];
-    a[5] = (jy + Fy) / n2[5];
+    const C Jx = FORCE ? jx + Fx : jx, Jy = FORCE ? jy + Fy : jy;
+    a[3] = Jx / n2[3];
+    a[5] = Jy / n2[5];
 #pragma unroll
     for (int k = 1; k < 9; k++) {
         if (k == 3 || k == 5) continue;
         const C sk = C(p.s[k]);
-        a[k] = (m[k] - sk * (m[k] - meq[k]) + (C(1) - C(0.5) * sk) * mf[k]) * (C(1) / n2[k]);
+        C r = m[k] - sk * (m[k] - meq[k]);
+        if constexpr (FORCE) r += (C(1) - C(0.5) * sk) * mf[k];
+        a[k] = r * (C(1) / n2[k]);
     }
     o[0] = a[0] - C(4) * a[1] + C(4) * a[2];
     const C Eax = a[0] - a[1] - C(2) * a[2], Edg = a[0] + C(2) * a[1] + a[2];
@@ -328,13 +345,18 @@ __device__ __forceinline__ void collide_mrt_d2q9(const C *h, C *o, const StepPar
     o[5] = E + O; o[6] = E - O;
     E = Edg - a[8]; O = -a[3] - a[4] + a[5] + a[6];
     o[7] = E + O; o[8] = E - O;
-    conserve<D2Q9, C>(o, drho, jx + Fx, jy + Fy, C(0));
+    conserve<D2Q9, C>(o, drho, Jx, Jy, C(0));
 }
 
 template <class L, class C>
 __device__ __forceinline__ void collide_mrt(const C *h, C *o, const StepParams &p) {
-    if constexpr (L::Q == 19) collide_mrt_d3q19<C>(h, o, p);
-    else collide_mrt_d2q9<C>(h, o, p);
+    if constexpr (L::Q == 19) {
+        if (p.has_force) collide_mrt_d3q19<C, true>(h, o, p);
+        else collide_mrt_d3q19<C, false>(h, o, p);
+    } else {
+        if (p.has_force) collide_mrt_d2q9<C, true>(h, o, p);
+        else collide_mrt_d2q9<C, false>(h, o, p);
+    }
 }
 
 // ---------------------------------------------------------------------------- ELBM
