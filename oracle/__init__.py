@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC = os.path.join(_HERE, "oracle.c")
 
 D2Q9, D3Q19 = 0, 1
-BGK, MRT, ELBM, SHANCHEN = 0, 1, 2, 3
+BGK, MRT, ELBM, SHANCHEN, REG, SMAG = 0, 1, 2, 3, 4, 5
 MLP_NPARAM = 1313
 MLP_NTOTAL = 1325  # weights + input normalisation mu[6], isd[6]
 
@@ -38,7 +38,8 @@ class Params(C.Structure):
                 ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("tau", C.c_double), ("g", C.c_double * 3), ("s", C.c_double * 19),
                 ("alpha_init", C.c_int), ("alpha_tol", C.c_double), ("alpha_maxit", C.c_int),
-                ("mlp", C.POINTER(C.c_double)), ("G", C.c_double), ("psi", C.c_int)]
+                ("mlp", C.POINTER(C.c_double)), ("G", C.c_double), ("psi", C.c_int),
+                ("cs_smag", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -173,7 +174,7 @@ class Oracle:
     """One simulation held by the oracle: parameters plus the population array."""
 
     def __init__(self, lattice, model, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), mrt_rates=None,
-                 alpha_init=0, alpha_tol=1e-10, alpha_maxit=20, mlp=None, G=0.0, psi=0):
+                 alpha_init=0, alpha_tol=1e-10, alpha_maxit=20, mlp=None, G=0.0, psi=0, cs_smag=0.1):
         self.p = Params()
         self.p.lattice, self.p.model = lattice, model
         self.p.nx, self.p.ny, self.p.nz = nx, ny, nz
@@ -187,6 +188,7 @@ class Oracle:
         self._mlp = _f64(mlp) if mlp is not None else None
         self.p.mlp = _dp(self._mlp) if mlp is not None else None
         self.p.G, self.p.psi = G, psi
+        self.p.cs_smag = cs_smag
         self.q = q_of(lattice)
         self.n = nx * ny * nz
         self.ncomp = 2 if model == SHANCHEN else 1
@@ -196,6 +198,7 @@ class Oracle:
 
     @classmethod
     def from_case(cls, case, **kw):
+        kw.setdefault("cs_smag", case.cs_smag)
         o = cls(case.lattice, case.model, case.nx, case.ny, case.nz, case.tau, case.force,
                 case.mrt_rates, G=case.G, psi=case.psi, **kw)
         if case.flags is not None:

@@ -29,6 +29,11 @@
  *  - ELBM relaxation f + alpha beta (feq - f), beta = 1/(2 tau), so alpha = 2 is LBGK.
  *  - Shan-Chen force F_A = -G psi_A sum_i w_i psi_B(x+e_i) e_i (G > 0 repulsive),
  *    EDM forcing around the common velocity.
+ *  - Regularized model: the non-equilibrium part is taken about the polynomial
+ *    equilibrium, and the step takes no body force (the paper pairs it with none; the
+ *    projection would drop the -F/2 first moment that Guo forcing relies on).
+ *  - Smagorinsky model: Q from the polynomial equilibrium at the force-shifted
+ *    velocity, and the Guo prefactor 1 - 1/(2 tau) with the local tau = tau0 + tau_t.
  */
 #include "oracle.h"
 
@@ -563,6 +568,44 @@ static void collide_single(const orc_params *P, const lattice_t *L, const double
         for (int i = 0; i < q; i++) out[i] = h[i] + omega * (heq[i] - h[i]) + pre * Fi[i];
         return;
     }
+    const double cs2 = 1.0 / 3.0;
+    if (P->model == ORC_REG) {
+        /* Regularized LBM subsection: the non-equilibrium part f_i - feq_i is replaced by
+         * w_i / (2 cs^4) (e_ia e_ib - cs^2 d_ab) Pi_ab, with
+         * Pi_ab = sum_i (f_i - feq_i) (e_ia e_ib - cs^2 d_ab); then the LBGK relaxation.
+         * The indices run over the lattice's D dimensions. */
+        double Pi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int i = 0; i < q; i++) {
+            double fneq = h[i] - heq[i];
+            for (int a = 0; a < L->d; a++)
+                for (int b = 0; b < L->d; b++) Pi[a][b] += fneq * (L->e[i][a] * L->e[i][b] - (a == b ? cs2 : 0.0));
+        }
+        double omega = 1.0 / P->tau;
+        for (int i = 0; i < q; i++) {
+            double s = 0.0;
+            for (int a = 0; a < L->d; a++)
+                for (int b = 0; b < L->d; b++) s += (L->e[i][a] * L->e[i][b] - (a == b ? cs2 : 0.0)) * Pi[a][b];
+            double hreg = heq[i] + L->w[i] / (2.0 * cs2 * cs2) * s; /* regularised state, as h */
+            out[i] = hreg + omega * (heq[i] - hreg);
+        }
+        return;
+    }
+    if (P->model == ORC_SMAG) {
+        /* Smagorinsky subgrid model: Q_ab = sum_i e_ia e_ib (f_i - feq_i),
+         * tau_t = (sqrt(tau0^2 + 4 cs^-4 C_S^2 (Q_ab Q_ab)^(1/2)) - tau0) / 2, and the LBGK
+         * step (with its Guo source) at tau = tau0 + tau_t. */
+        double Q[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, QQ = 0.0;
+        for (int i = 0; i < q; i++)
+            for (int a = 0; a < L->d; a++)
+                for (int b = 0; b < L->d; b++) Q[a][b] += L->e[i][a] * L->e[i][b] * (h[i] - heq[i]);
+        for (int a = 0; a < L->d; a++)
+            for (int b = 0; b < L->d; b++) QQ += Q[a][b] * Q[a][b];
+        double tau0 = P->tau;
+        double tau_t = 0.5 * (sqrt(tau0 * tau0 + 4.0 / (cs2 * cs2) * P->cs_smag * P->cs_smag * sqrt(QQ)) - tau0);
+        double tau = tau0 + tau_t, omega = 1.0 / tau, pre = 1.0 - 1.0 / (2.0 * tau);
+        for (int i = 0; i < q; i++) out[i] = h[i] + omega * (heq[i] - h[i]) + pre * Fi[i];
+        return;
+    }
     /* MRT: m = M h, m* = m - S (m - m_eq) + (I - S/2) M F~, h* = M^-1 m*,
      * with M^-1 = M^T diag(1/|row|^2) for the orthogonal basis (linear, so the same
      * as relaxing f with m_eq = M feq). */
@@ -630,11 +673,13 @@ void orc_collide_node_sc(const orc_params *P, const double *f2, const double *ps
 
 static int check_params(const orc_params *P) {
     if (P->lattice != ORC_D2Q9 && P->lattice != ORC_D3Q19) return -1;
-    if (P->model < ORC_BGK || P->model > ORC_SHANCHEN) return -1;
+    if (P->model < ORC_BGK || P->model > ORC_SMAG) return -1;
     if (P->nx <= 0 || P->ny <= 0 || P->nz <= 0) return -1;
     if (P->lattice == ORC_D2Q9 && P->nz != 1) return -1;
     if (!(P->tau > 0.5)) return -1;
-    if (P->model == ORC_ELBM && (P->g[0] != 0.0 || P->g[1] != 0.0 || P->g[2] != 0.0)) return -1;
+    if ((P->model == ORC_ELBM || P->model == ORC_REG) && (P->g[0] != 0.0 || P->g[1] != 0.0 || P->g[2] != 0.0))
+        return -1;
+    if (P->model == ORC_SMAG && !(P->cs_smag >= 0.0)) return -1;
     return 0;
 }
 

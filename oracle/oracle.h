@@ -17,8 +17,9 @@
  * (node n = x + nx*(y + ny*z)); flags[N] (0 fluid, 1 full-way bounce-back wall);
  * densities rho[C][N]; velocities u[3][N] (the z row is zero on D2Q9).
  *
- * Parity unpinned (no printed values in the paper): the MRT, ELBM and
- * Shan-Chen steps beyond the identities and closed forms the tests check.
+ * Parity unpinned (no printed values in the paper): the MRT, ELBM,
+ * Shan-Chen, regularized and Smagorinsky steps beyond the identities and
+ * closed forms the tests check.
  */
 #ifndef LBM_ORACLE_H
 #define LBM_ORACLE_H
@@ -29,7 +30,7 @@ extern "C" {
 #endif
 
 enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
-enum { ORC_BGK = 0, ORC_MRT = 1, ORC_ELBM = 2, ORC_SHANCHEN = 3 };
+enum { ORC_BGK = 0, ORC_MRT = 1, ORC_ELBM = 2, ORC_SHANCHEN = 3, ORC_REG = 4, ORC_SMAG = 5 };
 
 typedef struct {
     int lattice, model;
@@ -43,6 +44,7 @@ typedef struct {
     const double *mlp;    /* alpha_init == 2: 1325 MLP parameters (1313 weights, mu[6], isd[6]) */
     double G;             /* Shan-Chen coupling */
     int psi;              /* 0: psi = rho, 1: psi = 1 - exp(-rho) */
+    double cs_smag;       /* Smagorinsky constant C_S (ORC_SMAG) */
 } orc_params;
 
 typedef struct {

@@ -63,7 +63,7 @@ def uniform_pm(seed: int, stream: int, shape, amp: float, dtype=np.float64) -> n
 # ---------------------------------------------------------------------------
 # lattice identifiers shared with the C ABI (plain integers, no tables)
 D2Q9, D3Q19 = 0, 1
-BGK, MRT, ELBM, SHANCHEN = 0, 1, 2, 3
+BGK, MRT, ELBM, SHANCHEN, REG, SMAG = 0, 1, 2, 3, 4, 5
 FLUID, WALL = 0, 1
 Q_OF = {D2Q9: 9, D3Q19: 19}
 D_OF = {D2Q9: 2, D3Q19: 3}
@@ -93,6 +93,7 @@ class Case:
     mrt_rates: np.ndarray | None = None
     G: float = 0.0
     psi: int = 0
+    cs_smag: float = 0.1
     extra: dict = field(default_factory=dict)
 
     @property
@@ -168,6 +169,18 @@ def taylor_green_2d(nx, ny, u0):
     return np.ones((1, x.size)), u
 
 
+def kida_3d(n, u0):
+    """Kida's vortex on a periodic n^3 grid spanning (2 pi)^3, from the paper's Kida vortex
+    subsection: with (x, y, z) = 2 pi (i, j, k) / n,
+    u_x = u0 sin x (cos 3y cos z - cos y cos 3z), u_y and u_z by cyclic permutation; rho = 1."""
+    x, y, z = (2 * np.pi / n * a for a in _grid(n, n, n))
+    u = np.empty((3, x.size))
+    u[0] = u0 * np.sin(x) * (np.cos(3 * y) * np.cos(z) - np.cos(y) * np.cos(3 * z))
+    u[1] = u0 * np.sin(y) * (np.cos(3 * z) * np.cos(x) - np.cos(z) * np.cos(3 * x))
+    u[2] = u0 * np.sin(z) * (np.cos(3 * x) * np.cos(y) - np.cos(x) * np.cos(3 * y))
+    return np.ones((1, x.size)), u
+
+
 def random_state_fields(nx, ny, nz, d, seed, umax=0.05, drho=0.02, ncomp=1, stream0=0):
     """Smooth-free random macroscopic fields for parity tests (U(-umax, umax) velocity)."""
     n = nx * ny * nz
@@ -228,6 +241,15 @@ def c4_elbm_taylor_green(n=256, steps=1000, u0=0.05, nu=1e-5):
     rho, u = taylor_green_3d(n, n, n, u0)
     return Case("d3q19_elbm_taylor_green_%d" % n, D3Q19, ELBM, n, n, n, tau_from_nu(nu),
                 (0.0, 0.0, 0.0), steps, None, rho, u, extra={"u0": u0, "nu": nu})
+
+
+def kida_vortex(n=256, model=SMAG, re=1.28e5, u0=0.05, steps=1000, cs_smag=0.1):
+    """D3Q19 Kida vortex, periodic n^3, Re = n u0 / nu (the paper's validation and
+    lattice-performance case), run with the regularized or Smagorinsky BGK (or plain BGK)."""
+    rho, u = kida_3d(n, u0)
+    nu = n * u0 / re
+    return Case("d3q19_kida_%d_re%g" % (n, re), D3Q19, model, n, n, n, tau_from_nu(nu), (0.0, 0.0, 0.0),
+                steps, None, rho, u, cs_smag=cs_smag, extra={"u0": u0, "nu": nu, "re": re})
 
 
 def c5_shan_chen(n=384, steps=2000, G=0.9, amp=0.01, seed=DEFAULT_SEED, tau=1.0):

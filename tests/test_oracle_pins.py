@@ -146,7 +146,9 @@ def _mom(o, f):
 
 
 @pytest.mark.parametrize("lattice,model", [(S.D2Q9, S.BGK), (S.D3Q19, S.BGK), (S.D2Q9, S.MRT),
-                                           (S.D3Q19, S.MRT), (S.D2Q9, S.ELBM), (S.D3Q19, S.ELBM)])
+                                           (S.D3Q19, S.MRT), (S.D2Q9, S.ELBM), (S.D3Q19, S.ELBM),
+                                           (S.D2Q9, S.REG), (S.D3Q19, S.REG), (S.D2Q9, S.SMAG),
+                                           (S.D3Q19, S.SMAG)])
 def test_conservation_periodic(lattice, model):
     nz = 1 if lattice == S.D2Q9 else 6
     rates = (S.mrt_rates_d2q9 if lattice == S.D2Q9 else S.mrt_rates_d3q19)(1 / 0.7, 1.3)
@@ -167,7 +169,8 @@ def test_conservation_with_walls_and_force_momentum_budget():
     assert abs(o.f.sum() - m0) <= 1e-13 * m0
 
 
-@pytest.mark.parametrize("lattice,model", [(S.D2Q9, S.BGK), (S.D3Q19, S.MRT)])
+@pytest.mark.parametrize("lattice,model", [(S.D2Q9, S.BGK), (S.D3Q19, S.MRT), (S.D2Q9, S.SMAG),
+                                           (S.D3Q19, S.SMAG)])
 def test_guo_force_adds_exactly_F_per_step(lattice, model):
     """Periodic, no walls: total momentum grows by sum_x rho g each step."""
     nz = 1 if lattice == S.D2Q9 else 5
@@ -183,7 +186,8 @@ def test_guo_force_adds_exactly_F_per_step(lattice, model):
 
 
 @pytest.mark.parametrize("lattice,model", [(S.D2Q9, S.BGK), (S.D3Q19, S.BGK), (S.D3Q19, S.MRT),
-                                           (S.D3Q19, S.ELBM)])
+                                           (S.D3Q19, S.ELBM), (S.D2Q9, S.REG), (S.D3Q19, S.REG),
+                                           (S.D3Q19, S.SMAG)])
 def test_rest_state_is_fixed_point(lattice, model):
     nz = 1 if lattice == S.D2Q9 else 4
     o = oracle.Oracle(lattice, model, 5, 4, nz, 0.6, mrt_rates=S.mrt_rates_d3q19(1 / 0.6, 1.2))
@@ -631,3 +635,175 @@ def test_single_node_shan_chen_matches_full_step():
         post = o.collide_node_sc(f0[:, :, node], psi_nb)
         for i in range(19):
             np.testing.assert_allclose(o.f[:, i, nb[i]], post[:, i], rtol=0, atol=3e-17)
+
+
+# --------------------------------------------------------------------------- regularized and Smagorinsky LBGK
+
+def _d(lattice):
+    return 2 if lattice == S.D2Q9 else 3
+
+
+def _hermite2(lattice, Pi):
+    """w_i (e_i e_i - I/3) : Pi / (2 cs^4): non-equilibrium content whose stress is Pi."""
+    e, w, _ = oracle.tables(lattice)
+    d = _d(lattice)
+    E = e[:, :d].astype(float)
+    Hq = np.einsum("ia,ib->iab", E, E) - np.eye(d) / 3.0
+    return 4.5 * w * np.einsum("iab,ab->i", Hq, Pi[:d, :d])
+
+
+def _stress(lattice, g):
+    """sum_i g_i (e_i e_i - I/3), D x D."""
+    e, _, _ = oracle.tables(lattice)
+    d = _d(lattice)
+    E = e[:, :d].astype(float)
+    return np.einsum("i,iab->ab", g, np.einsum("ia,ib->iab", E, E) - np.eye(d) / 3.0)
+
+
+def _sym(rng, d, amp, kind="full"):
+    A = amp * (2 * rng.random((d, d)) - 1)
+    A = A + A.T
+    if kind == "diag":
+        A = np.diag(np.diag(A))
+    elif kind == "offdiag":
+        A = A - np.diag(np.diag(A))
+    P = np.zeros((3, 3))
+    P[:d, :d] = A
+    return P
+
+
+def _macro_state(lattice, rng):
+    d = _d(lattice)
+    u = np.zeros(3)
+    u[:d] = 0.08 * (2 * rng.random(d) - 1)
+    return 0.95 + 0.1 * rng.random(), u
+
+
+@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
+def test_regularized_keeps_second_order_nonequilibrium(lattice):
+    """f - feq already of the regularized form: the projection is the identity, so the
+    regularized step is the LBGK step."""
+    rng = np.random.default_rng(21)
+    ob = oracle.Oracle(lattice, S.BGK, 1, 1, 1, 0.71)
+    orr = oracle.Oracle(lattice, S.REG, 1, 1, 1, 0.71)
+    for _ in range(20):
+        rho, u = _macro_state(lattice, rng)
+        f = oracle.feq(lattice, rho, u) + _hermite2(lattice, _sym(rng, _d(lattice), 2e-3))
+        np.testing.assert_allclose(orr.collide_node(f), ob.collide_node(f), rtol=0, atol=4e-16)
+
+
+@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
+def test_regularized_drops_ghost_content(lattice):
+    """Non-equilibrium content with no mass, momentum or second moment is removed: the
+    regularized step returns feq exactly, where LBGK keeps (1 - omega) of it."""
+    e, w, _ = oracle.tables(lattice)
+    q, d = len(w), _d(lattice)
+    rows = [np.ones(q)] + [e[:, a] for a in range(d)] + [e[:, a] * e[:, b] for a in range(d) for b in range(a, d)]
+    A = np.array(rows, dtype=float)
+    rng = np.random.default_rng(22)
+    ob = oracle.Oracle(lattice, S.BGK, 1, 1, 1, 0.71)
+    orr = oracle.Oracle(lattice, S.REG, 1, 1, 1, 0.71)
+    for _ in range(10):
+        g = 1e-3 * (2 * rng.random(q) - 1)
+        g -= A.T @ np.linalg.solve(A @ A.T, A @ g)
+        assert np.abs(A @ g).max() < 1e-17
+        rho, u = _macro_state(lattice, rng)
+        fe = oracle.feq(lattice, rho, u)
+        np.testing.assert_allclose(orr.collide_node(fe + g), fe, rtol=0, atol=4e-16)
+        assert np.abs(ob.collide_node(fe + g) - fe).max() > 1e-5
+
+
+@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
+def test_regularized_relaxes_stress_by_one_minus_omega(lattice):
+    """Any state: afterwards f - feq is of the regularized form, with stress (1 - omega)
+    times the incoming one; mass and momentum are unchanged."""
+    e, w, _ = oracle.tables(lattice)
+    q, d, tau = len(w), _d(lattice), 0.63
+    orr = oracle.Oracle(lattice, S.REG, 1, 1, 1, tau)
+    rng = np.random.default_rng(23)
+    for _ in range(20):
+        f = w * (1 + 0.3 * (2 * rng.random(q) - 1))
+        rho = f.sum()
+        u = np.zeros(3)
+        u[:d] = (e[:, :d].T @ f) / rho
+        fe = oracle.feq(lattice, rho, u)
+        out = orr.collide_node(f)
+        Pin, Pout = _stress(lattice, f - fe), _stress(lattice, out - fe)
+        np.testing.assert_allclose(Pout, (1 - 1 / tau) * Pin, rtol=0, atol=1e-15)
+        full = np.zeros((3, 3))
+        full[:d, :d] = Pout
+        np.testing.assert_allclose(out - fe, _hermite2(lattice, full), rtol=0, atol=1e-15)
+        assert abs(out.sum() - rho) < 1e-15
+        np.testing.assert_allclose(e[:, :d].T @ out, rho * u[:d], rtol=0, atol=1e-15)
+
+
+def test_regularized_rejects_body_force():
+    o = oracle.Oracle(S.D3Q19, S.REG, 4, 4, 4, 0.7, (1e-5, 0.0, 0.0))
+    with pytest.raises(ValueError):
+        o.init_eq(*S.rest_fields(4, 4, 4, 3))
+
+
+@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
+def test_smagorinsky_with_zero_constant_is_bgk(lattice):
+    g = (2e-4, -1e-4, 3e-4 if lattice == S.D3Q19 else 0.0)
+    ob = oracle.Oracle(lattice, S.BGK, 1, 1, 1, 0.57, g)
+    osm = oracle.Oracle(lattice, S.SMAG, 1, 1, 1, 0.57, g, cs_smag=0.0)
+    _, w, _ = oracle.tables(lattice)
+    rng = np.random.default_rng(24)
+    for _ in range(20):
+        f = w * (1 + 0.3 * (2 * rng.random(len(w)) - 1))
+        np.testing.assert_allclose(osm.collide_node(f), ob.collide_node(f), rtol=0, atol=4e-16)
+
+
+@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
+@pytest.mark.parametrize("kind", ["diag", "offdiag", "full"])
+def test_smagorinsky_effective_tau_closed_form(lattice, kind):
+    """f = feq + content of stress Pi has momentum flux Q = Pi exactly (fourth-order
+    isotropy), so the step is feq + (1 - 1/tau)(f - feq) with the subgrid model's
+    tau = tau0 + tau_t, tau_t = (sqrt(tau0^2 + 4 cs^-4 C^2 |Pi|) - tau0) / 2."""
+    tau0, cs = 0.5003, 0.4
+    osm = oracle.Oracle(lattice, S.SMAG, 1, 1, 1, tau0, cs_smag=cs)
+    rng = np.random.default_rng(25)
+    for _ in range(10):
+        rho, u = _macro_state(lattice, rng)
+        Pi = _sym(rng, _d(lattice), 1.0, kind)
+        Pi *= 2e-2 / np.sqrt((Pi ** 2).sum())
+        fe = oracle.feq(lattice, rho, u)
+        g = _hermite2(lattice, Pi)
+        out = osm.collide_node(fe + g)
+        r = (out - fe) @ g / (g @ g)
+        tau = tau0 + 0.5 * (np.sqrt(tau0 ** 2 + 36.0 * cs ** 2 * np.sqrt((Pi ** 2).sum())) - tau0)
+        assert tau > tau0 * 1.05
+        assert abs(r - (1 - 1 / tau)) < 1e-12
+        np.testing.assert_allclose(out - fe, r * g, rtol=0, atol=1e-15)
+
+
+def test_smagorinsky_dissipates_more_than_bgk():
+    """Kida vortex at high Reynolds number: the eddy viscosity only adds dissipation."""
+    n = 12
+    ke = {}
+    for model in (S.BGK, S.SMAG):
+        c = S.kida_vortex(n, model, re=1e5, u0=0.05)
+        o = oracle.Oracle.from_case(c)
+        o.run(40)
+        rho, u = o.macro()
+        ke[model] = 0.5 * (rho[0] * (u ** 2).sum(0)).mean()
+    assert ke[S.SMAG] < ke[S.BGK] * (1 - 1e-4)
+
+
+def test_kida_initial_field():
+    """Kida's field: mean kinetic energy 3 u0^2 / 8 and zero divergence (spectral)."""
+    n, u0 = 24, 0.05
+    rho, u = S.kida_3d(n, u0)
+    assert abs(0.5 * (u ** 2).sum(0).mean() - 3 * u0 ** 2 / 8) < 1e-17
+    k = np.fft.fftfreq(n, 1.0 / n)
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    U = [np.fft.fftn(u[a].reshape(n, n, n)) for a in range(3)]
+    div = np.fft.ifftn(1j * (kx * U[0] + ky * U[1] + kz * U[2])).real
+    assert np.abs(div).max() < 1e-15
+    # the cyclic structure: u_y(x, y, z) = u_x(y, z, x) and u_z(x, y, z) = u_y(y, z, x);
+    # arrays are [z][y][x], so that is a cyclic permutation of the axes
+    ux, uy, uz = (u[a].reshape(n, n, n) for a in range(3))
+    np.testing.assert_array_equal(uy, ux.transpose(1, 2, 0))
+    np.testing.assert_array_equal(uz, uy.transpose(1, 2, 0))
+    assert np.abs(ux).max() > 0.1 * u0
