@@ -159,6 +159,26 @@ def run_extras(P, S, stream, torch):
                                              "steps": 100,
                                              "mass_rel_change": [float(abs(d1[c] - d0[c]) / d0[c]) for c in (0, 1)]}
     print("[bench] Shan-Chen done", file=sys.stderr, flush=True)
+
+    # D3Q19 Kida vortex 256^3, FP32 storage, AB and AA: LBGK and regularized LBGK at
+    # Re 4000, Smagorinsky LBGK (C_S = 0.1) at Re 1.28e5
+    kida = {}
+    for model, re, name in [(S.BGK, 4000.0, "bgk_re4000"), (S.REG, 4000.0, "regularized_re4000"),
+                            (S.SMAG, 1.28e5, "smagorinsky_re128000")]:
+        ck = S.kida_vortex(256, model, re=re)
+        for lay, tag in [(P.LBM_AB, ""), (P.LBM_AA, "_aa")]:
+            s = P.Sim.from_case(ck, P.LBM_F32, lay, stream=stream)
+            ke0 = s.diag()[5]
+            s.step(20)
+            ms = _time_steps(s, stream, torch, 200)
+            d = s.diag()
+            s.close()
+            kida[name + tag] = {"mlups": round(ck.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                                "bytes_per_node": 152, "hbm_gbs_algorithmic": round(152 * ck.n / (ms * 1e-3) / 1e9, 1),
+                                "tau": round(ck.tau, 6), "ke_ratio_after_220_steps": float(d[5] / ke0),
+                                "nonfinite_nodes": int(d[6])}
+    out["d3q19_kida_256_fp32"] = kida
+    print("[bench] Kida done", file=sys.stderr, flush=True)
     return out
 
 

@@ -6,7 +6,8 @@
  * per node, gather the populations that stream in, compute the macroscopic moments
  * (section 2, macroscopic-field equation), relax towards equilibrium (LBGK equation
  * with the sign of the GPU kernel algorithm; MRT collision equation; entropic LBM
- * equations; Shan-Chen force equation), apply full-way bounce-back on wall nodes
+ * equations; Shan-Chen force equation; the regularized and Smagorinsky variants of
+ * LBGK from the enhanced-stability subsections), apply full-way bounce-back on wall nodes
  * (boundary-conditions subsection), and store.  Body forces use Guo's scheme (force
  * equation of the body-forces subsection), Shan-Chen uses the exact difference method.
  *
@@ -43,7 +44,12 @@ extern "C" {
 typedef struct lbm_sim lbm_sim; /* opaque; owned by the library */
 
 enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
-enum { LBM_BGK = 0, LBM_MRT = 1, LBM_ELBM = 2, LBM_SHANCHEN = 3 };
+/* Collision models: LBGK, MRT, entropic LBGK, two-component Shan-Chen, regularized LBGK
+ * (the non-equilibrium part replaced by its second-order projection w_i/(2 cs^4)
+ * (e_i e_i - cs^2 I):Pi_neq before relaxing; regularized-LBM subsection) and
+ * Smagorinsky LBGK (local tau = tau0 + tau_t from the momentum flux of f - feq,
+ * Smagorinsky-subgrid equations). */
+enum { LBM_BGK = 0, LBM_MRT = 1, LBM_ELBM = 2, LBM_SHANCHEN = 3, LBM_REGULARIZED = 4, LBM_SMAGORINSKY = 5 };
 /* Storage of the populations in HBM.  S = shifted: the stored value is f_i - w_i (the
  * round-off minimising formulation of the precision subsection); compute is FP32 for
  * every storage except F64. */
@@ -65,7 +71,8 @@ enum {
 /* Create a simulation.  lattice LBM_D2Q9 needs nz == 1.  tau > 1/2 is the relaxation
  * time (for MRT the stress-moment rate is 1/tau unless lbm_set_mrt_rates says
  * otherwise).  force[3] is a uniform body acceleration g (force density rho g); NULL
- * means zero; force[2] is ignored on D2Q9.  ELBM takes no force.  Nothing is allocated
+ * means zero; force[2] is ignored on D2Q9.  ELBM and the regularized model take no
+ * force (LBM_EUNSUPPORTED).  Nothing is allocated
  * on the device until lbm_init_eq() or lbm_set_f().  *out receives the handle. */
 int lbm_create(int lattice, int model, int nx, int ny, int nz, double tau,
                const double *force, lbm_sim **out);
@@ -90,6 +97,13 @@ int lbm_set_elbm(lbm_sim *sim, int alpha_init, double tol, int max_iter);
 /* Shan-Chen: coupling G (G > 0 repulsive) and pseudopotential psi (0: rho,
  * 1: 1 - exp(-rho)).  Default G = 0, psi = 0. */
 int lbm_set_shanchen(lbm_sim *sim, double G, int psi);
+
+/* Smagorinsky constant C_S >= 0 of the LBM_SMAGORINSKY model (subgrid-model
+ * subsection): tau_t = (sqrt(tau0^2 + 4 cs^-4 C_S^2 |Q|) - tau0)/2 with
+ * Q_ab = sum_i e_ia e_ib (f_i - feq_i), |Q| = (Q_ab Q_ab)^(1/2), tau = tau0 + tau_t, and the
+ * LBGK step (Guo source included) at that tau.  C_S = 0 is LBGK.  Default 0.1.  Other
+ * models: LBM_EUNSUPPORTED. */
+int lbm_set_smagorinsky(lbm_sim *sim, double cs);
 
 /* HIP stream (hipStream_t cast to void*) for every launch and copy of this handle;
  * NULL = the null stream. */

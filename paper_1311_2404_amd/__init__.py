@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_D2Q9, LBM_D3Q19 = 0, 1
-LBM_BGK, LBM_MRT, LBM_ELBM, LBM_SHANCHEN = 0, 1, 2, 3
+LBM_BGK, LBM_MRT, LBM_ELBM, LBM_SHANCHEN, LBM_REGULARIZED, LBM_SMAGORINSKY = 0, 1, 2, 3, 4, 5
 LBM_F64, LBM_F32, LBM_F32S, LBM_BF16S, LBM_F16S = 0, 1, 2, 3, 4
 LBM_AB, LBM_AA = 0, 1
 LBM_FLUID, LBM_WALL_BB = 0, 1
@@ -36,6 +36,7 @@ _SIGS = [
     ("lbm_set_mrt_rates", C.c_int, [_vp, _dp, C.c_int]),
     ("lbm_set_elbm", C.c_int, [_vp, C.c_int, C.c_double, C.c_int]),
     ("lbm_set_shanchen", C.c_int, [_vp, C.c_double, C.c_int]),
+    ("lbm_set_smagorinsky", C.c_int, [_vp, C.c_double]),
     ("lbm_set_stream", C.c_int, [_vp, _vp]),
     ("lbm_set_flags", C.c_int, [_vp, C.POINTER(C.c_uint8)]),
     ("lbm_init_eq", C.c_int, [_vp, _dp, _dp, _dp]),
@@ -135,6 +136,10 @@ def lbm_set_elbm(sim, alpha_init=0, tol=1e-10, max_iter=20):
 
 def lbm_set_shanchen(sim, G, psi=0):
     _err(sim, lib().lbm_set_shanchen(sim, G, psi))
+
+
+def lbm_set_smagorinsky(sim, cs):
+    _err(sim, lib().lbm_set_smagorinsky(sim, cs))
 
 
 def lbm_set_stream(sim, stream):
@@ -298,6 +303,8 @@ class Sim:
             lbm_set_mrt_rates(s.h, case.mrt_rates)
         if case.model == LBM_SHANCHEN:
             lbm_set_shanchen(s.h, case.G, case.psi)
+        if case.model == LBM_SMAGORINSKY:
+            lbm_set_smagorinsky(s.h, case.cs_smag)
         if case.flags is not None:
             lbm_set_flags(s.h, case.flags)
         if init:

@@ -32,6 +32,7 @@ struct lbm_sim {
     int alpha_maxit = 20;
     double G = 0.0;
     int psi_mode = 0;
+    double cs_smag = 0.1;  // Smagorinsky constant
     hipStream_t stream = nullptr;
     int device = 0;
     void *buf[2] = {nullptr, nullptr};
@@ -137,6 +138,8 @@ StepParams base_params(const lbm_sim *s) {
     for (int a = 0; a < 3; a++) p.g[a] = s->g[a];
     p.has_force = (s->g[0] != 0.0 || s->g[1] != 0.0 || s->g[2] != 0.0) ? 1 : 0;
     for (int k = 0; k < 19; k++) p.s[k] = s->s[k];
+    p.tau0 = s->tau;
+    p.smag_k = 36.0 * s->cs_smag * s->cs_smag;
     p.beta = 0.5 / s->tau;
     p.alpha_tol = s->alpha_tol;
     p.alpha_maxit = s->alpha_maxit;
@@ -297,7 +300,7 @@ int lbm_create(int lattice, int model, int nx, int ny, int nz, double tau, const
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
     *out = nullptr;
     if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(nullptr, LBM_EINVAL, "unknown lattice");
-    if (model < LBM_BGK || model > LBM_SHANCHEN) return fail(nullptr, LBM_EINVAL, "unknown model");
+    if (model < LBM_BGK || model > LBM_SMAGORINSKY) return fail(nullptr, LBM_EINVAL, "unknown model");
     if (nx <= 0 || ny <= 0 || nz <= 0) return fail(nullptr, LBM_EINVAL, "grid sizes must be positive");
     if (lattice == LBM_D2Q9 && nz != 1) return fail(nullptr, LBM_EINVAL, "D2Q9 needs nz == 1");
     if (nz > 65535 || ny > 65535) return fail(nullptr, LBM_EINVAL, "ny and nz must be <= 65535");
@@ -313,6 +316,8 @@ int lbm_create(int lattice, int model, int nx, int ny, int nz, double tau, const
     }
     if (model == LBM_ELBM && (g[0] != 0 || g[1] != 0 || g[2] != 0))
         return fail(nullptr, LBM_EUNSUPPORTED, "the entropic model takes no body force");
+    if (model == LBM_REGULARIZED && (g[0] != 0 || g[1] != 0 || g[2] != 0))
+        return fail(nullptr, LBM_EUNSUPPORTED, "the regularized model takes no body force");
     lbm_sim *s = new (std::nothrow) lbm_sim();
     if (!s) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
     s->lattice = lattice;
@@ -373,6 +378,14 @@ int lbm_set_shanchen(lbm_sim *s, double G, int psi) {
     if (!std::isfinite(G) || (psi != 0 && psi != 1)) return fail(s, LBM_EINVAL, "bad G or psi");
     s->G = G;
     s->psi_mode = psi;
+    return LBM_OK;
+}
+
+int lbm_set_smagorinsky(lbm_sim *s, double cs) {
+    if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
+    if (s->model != LBM_SMAGORINSKY) return fail(s, LBM_EUNSUPPORTED, "the constant belongs to the Smagorinsky model");
+    if (!std::isfinite(cs) || cs < 0.0) return fail(s, LBM_EINVAL, "C_S must be finite and >= 0");
+    s->cs_smag = cs;
     return LBM_OK;
 }
 
@@ -486,6 +499,8 @@ int lbm_step(lbm_sim *s, int n) {
         switch (s->model) {
         case LBM_BGK: e = launch_step_bgk(s->lattice, s->storage, s->sr, lay, s->has_walls, p, cfg); break;
         case LBM_MRT: e = launch_step_mrt(s->lattice, s->storage, s->sr, lay, s->has_walls, p, cfg); break;
+        case LBM_REGULARIZED: e = launch_step_reg(s->lattice, s->storage, s->sr, lay, s->has_walls, p, cfg); break;
+        case LBM_SMAGORINSKY: e = launch_step_smag(s->lattice, s->storage, s->sr, lay, s->has_walls, p, cfg); break;
         case LBM_ELBM: e = launch_step_elbm(s->lattice, s->storage, lay, s->has_walls, p, cfg); break;
         default:
             e = launch_psi(s->lattice, s->storage, lay, p, cfg);

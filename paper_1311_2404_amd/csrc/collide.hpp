@@ -141,6 +141,122 @@ __device__ __forceinline__ void collide_bgk(const C *h, C *o, const StepParams &
     else collide_bgk_body<L, C, false>(h, o, p);
 }
 
+// ------------------------------------------------------------ regularized and Smagorinsky
+// Sums over the populations of the non-equilibrium part fn_i = h_i - heq_i: s0 = sum fn,
+// and the second moments sum fn e_a e_b.  With e_a in {-1, 0, 1}, e_a^2 is 1 or 0 and
+// e_a e_b is +-1 or 0, so every term is an add or a subtract.
+template <class C>
+struct NeqMoments {
+    C s0, xx, yy, zz, xy, xz, yz;
+};
+
+template <class L, class C>
+__device__ __forceinline__ void neq_moments_add(NeqMoments<C> &q, int i, C fn) {
+    q.s0 += fn;
+    if (L::ex(i) != 0) q.xx += fn;
+    if (L::ey(i) != 0) q.yy += fn;
+    if (L::ez(i) != 0) q.zz += fn;
+    if (L::ex(i) * L::ey(i) == 1) q.xy += fn;
+    if (L::ex(i) * L::ey(i) == -1) q.xy -= fn;
+    if (L::ex(i) * L::ez(i) == 1) q.xz += fn;
+    if (L::ex(i) * L::ez(i) == -1) q.xz -= fn;
+    if (L::ey(i) * L::ez(i) == 1) q.yz += fn;
+    if (L::ey(i) * L::ez(i) == -1) q.yz -= fn;
+}
+
+// Regularized LBGK (regularized LBM subsection): the non-equilibrium part is replaced by
+// w_i / (2 cs^4) (e_ia e_ib - cs^2 d_ab) Pi_ab, Pi_ab = sum_i fn_i (e_ia e_ib - cs^2 d_ab),
+// then relaxed as in LBGK: h* = heq + (1 - omega) h_reg.  No body force (the API rejects
+// one for this model).  Mass and momentum of h_reg vanish in exact arithmetic; conserve()
+// removes the rounding, as for LBGK.
+template <class L, class C>
+__device__ __forceinline__ void collide_reg(const C *h, C *o, const StepParams &p) {
+    const Macro<C> m = moments<L, C>(h);
+    const C irho = C(1) / m.rho;
+    const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
+    const C usq15 = C(1.5) * (vx * vx + vy * vy + vz * vz);
+    C heq[L::Q];
+    NeqMoments<C> q{C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const C eu = C(L::ex(i)) * vx + C(L::ey(i)) * vy + C(L::ez(i)) * vz;
+        heq[i] = C(L::w(i)) * (m.drho + m.rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
+        neq_moments_add<L, C>(q, i, h[i] - heq[i]);
+    }
+    const C t = q.s0 * C(1.0 / 3.0);
+    const C Pxx = q.xx - t, Pyy = q.yy - t, Pzz = L::D == 3 ? q.zz - t : C(0);
+    const C tr3 = (Pxx + Pyy + Pzz) * C(1.0 / 3.0);
+    const C k = (C(1) - C(p.omega)) * C(4.5);  // (1 - omega) / (2 cs^4)
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        C s = -tr3;
+        if (L::ex(i) != 0) s += Pxx;
+        if (L::ey(i) != 0) s += Pyy;
+        if (L::ez(i) != 0) s += Pzz;
+        if (L::ex(i) * L::ey(i) != 0) s += C(2 * L::ex(i) * L::ey(i)) * q.xy;
+        if (L::ex(i) * L::ez(i) != 0) s += C(2 * L::ex(i) * L::ez(i)) * q.xz;
+        if (L::ey(i) * L::ez(i) != 0) s += C(2 * L::ey(i) * L::ez(i)) * q.yz;
+        o[i] = heq[i] + k * C(L::w(i)) * s;
+    }
+    conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
+}
+
+// Smagorinsky LBGK (Smagorinsky subgrid subsection): Q_ab = sum_i e_ia e_ib fn_i and the
+// local relaxation time tau = tau0 + tau_t, tau_t = (sqrt(tau0^2 + 4 cs^-4 C_S^2 |Q|) -
+// tau0) / 2, |Q| = (Q_ab Q_ab)^(1/2); evaluated as (tau0 + sqrt(tau0^2 + k |Q|)) / 2,
+// which avoids the cancellation of the difference.  Then the LBGK step with its Guo
+// source at that tau.
+template <class L, class C, bool FORCE>
+__device__ __forceinline__ void collide_smag_body(const C *h, C *o, const StepParams &p) {
+    const Macro<C> m = moments<L, C>(h);
+    const C irho = C(1) / m.rho;
+    C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
+    C Fx = C(0), Fy = C(0), Fz = C(0);
+    if constexpr (FORCE) {
+        const C gx = C(p.g[0]), gy = C(p.g[1]), gz = C(L::D == 3 ? p.g[2] : 0.0);
+        vx += C(0.5) * gx;
+        vy += C(0.5) * gy;
+        vz += C(0.5) * gz;
+        Fx = m.rho * gx;
+        Fy = m.rho * gy;
+        Fz = m.rho * gz;
+    }
+    const C usq15 = C(1.5) * (vx * vx + vy * vy + vz * vz);
+    C heq[L::Q];
+    NeqMoments<C> q{C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const C eu = C(L::ex(i)) * vx + C(L::ey(i)) * vy + C(L::ez(i)) * vz;
+        heq[i] = C(L::w(i)) * (m.drho + m.rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
+        neq_moments_add<L, C>(q, i, h[i] - heq[i]);
+    }
+    C QQ = q.xx * q.xx + q.yy * q.yy + C(2) * q.xy * q.xy;
+    if constexpr (L::D == 3) QQ += q.zz * q.zz + C(2) * (q.xz * q.xz + q.yz * q.yz);
+    const C tau0 = C(p.tau0);
+    const C tau = C(0.5) * (tau0 + sqrt(tau0 * tau0 + C(p.smag_k) * sqrt(QQ)));
+    const C omega = C(1) / tau;
+    [[maybe_unused]] const C pre = C(1) - C(0.5) * omega;
+    [[maybe_unused]] const C vF = vx * Fx + vy * Fy + vz * Fz;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        C r = h[i] + omega * (heq[i] - h[i]);
+        if constexpr (FORCE) {
+            const C eu = C(L::ex(i)) * vx + C(L::ey(i)) * vy + C(L::ez(i)) * vz;
+            const C eF = C(L::ex(i)) * Fx + C(L::ey(i)) * Fy + C(L::ez(i)) * Fz;
+            r += pre * C(L::w(i)) * (C(3) * (eF - vF) + C(9) * eu * eF);
+        }
+        o[i] = r;
+    }
+    if constexpr (FORCE) conserve<L, C>(o, m.drho, m.jx + Fx, m.jy + Fy, m.jz + Fz);
+    else conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
+}
+
+template <class L, class C>
+__device__ __forceinline__ void collide_smag(const C *h, C *o, const StepParams &p) {
+    if (p.has_force) collide_smag_body<L, C, true>(h, o, p);
+    else collide_smag_body<L, C, false>(h, o, p);
+}
+
 // ---------------------------------------------------------------------------- MRT
 // D3Q19 basis rows (q = |e|^2): 1, 19q-30, (21q^2-53q+24)/2, ex, (5q-9)ex, ey,
 // (5q-9)ey, ez, (5q-9)ez, 3ex^2-q, (3q-5)(3ex^2-q), ey^2-ez^2, (3q-5)(ey^2-ez^2),

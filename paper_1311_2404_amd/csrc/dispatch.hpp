@@ -57,6 +57,11 @@ hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, bool fl
                            const LaunchCfg &c);
 hipError_t launch_step_mrt(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
                            const LaunchCfg &c);
+// step_reg.hip, step_smag.hip
+hipError_t launch_step_reg(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+                           const LaunchCfg &c);
+hipError_t launch_step_smag(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+                            const LaunchCfg &c);
 hipError_t launch_step_elbm(int lattice, int storage, int layout, bool flags, const StepParams &p,
                             const LaunchCfg &c);
 hipError_t launch_step_sc(int lattice, int storage, int layout, const StepParams &p, const LaunchCfg &c);

@@ -5,7 +5,7 @@
 namespace lbm {
 
 enum Layout { LAYOUT_AB = 0, LAYOUT_AA_EVEN = 1, LAYOUT_AA_ODD = 2 };
-enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3 };
+enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3, M_REG = 4, M_SMAG = 5 };
 
 constexpr int MLP_IN = 6;
 constexpr int MLP_H = 32;
@@ -32,6 +32,8 @@ struct StepParams {
     double g[3];                // body acceleration
     int has_force;
     double s[19];               // MRT rates in moment order
+    double tau0;                // Smagorinsky: base relaxation time
+    double smag_k;              // Smagorinsky: 4 cs^-4 C_S^2 = 36 C_S^2
     // entropic LBM
     double beta;                // 1/(2 tau)
     double alpha_tol;

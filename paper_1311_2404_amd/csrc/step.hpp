@@ -231,6 +231,10 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                 collide_bgk<L, C>(h, o, p);
             } else if constexpr (MODEL == M_MRT) {
                 collide_mrt<L, C>(h, o, p);
+            } else if constexpr (MODEL == M_REG) {
+                collide_reg<L, C>(h, o, p);
+            } else if constexpr (MODEL == M_SMAG) {
+                collide_smag<L, C>(h, o, p);
             } else {
                 const Macro<C> m = moments<L, C>(h);
                 const C irho = C(1) / m.rho;
@@ -477,6 +481,25 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
             LBM_STORE(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), rnd));
         }
     }
+}
+
+// Launches k_step<MODEL> for every lattice, storage (with the stochastic-rounding
+// variants), layout and flag mode; one translation unit per model instantiates it.
+template <int MODEL>
+hipError_t launch_k_step(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+                         const LaunchCfg &c) {
+    return with_lattice(lattice, [&](auto lt) {
+        using L = decltype(lt);
+        return with_storage<true>(storage, sr, [&](auto st) {
+            using St = decltype(st);
+            return with_layout(layout, [&](auto lay) {
+                constexpr int LAY = decltype(lay)::value;
+                if (flags) k_step<L, St, MODEL, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
+                else k_step<L, St, MODEL, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                return hipGetLastError();
+            });
+        });
+    });
 }
 
 }  // namespace lbm

@@ -1,0 +1,12 @@
+// Step-kernel instantiations for the regularized LBGK collision (all storages, layouts, flag modes).
+#include "dispatch.hpp"
+#include "step.hpp"
+
+namespace lbm {
+
+hipError_t launch_step_reg(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+                           const LaunchCfg &c) {
+    return launch_k_step<M_REG>(lattice, storage, sr, layout, flags, p, c);
+}
+
+}  // namespace lbm

@@ -102,3 +102,26 @@ def test_shan_chen_rejects_walls_and_sr(lbm):
         assert ei.value.code == lbm.LBM_EINVAL
     finally:
         lbm.lbm_destroy(h)
+
+
+def test_regularized_and_smagorinsky_arguments(lbm):
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_REGULARIZED, 4, 4, 4, 0.6, (0, 1e-5, 0))
+    assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    h = lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_BGK, 4, 4, 4, 0.6)
+    try:
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_smagorinsky(h, 0.1)
+        assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    finally:
+        lbm.lbm_destroy(h)
+    h = lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_SMAGORINSKY, 4, 4, 4, 0.6, (0, 1e-5, 0))
+    try:
+        lbm.lbm_set_smagorinsky(h, 0.0)
+        lbm.lbm_set_smagorinsky(h, 0.17)
+        for bad in (-0.1, float("nan"), float("inf")):
+            with pytest.raises(lbm.LbmError) as ei:
+                lbm.lbm_set_smagorinsky(h, bad)
+            assert ei.value.code == lbm.LBM_EINVAL
+    finally:
+        lbm.lbm_destroy(h)

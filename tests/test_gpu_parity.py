@@ -188,7 +188,7 @@ _LAYOUT_ENVS = [
 _LAYOUT_KEYS = ("LBM_POP_LAYOUT", "LBM_POP_PAD", "LBM_ROW_PAD", "LBM_BLOCK_PAD", "LBM_ROW_TILE")
 
 
-@pytest.mark.parametrize("model", [S.BGK, S.MRT, S.SHANCHEN, S.ELBM])
+@pytest.mark.parametrize("model", [S.BGK, S.MRT, S.SHANCHEN, S.ELBM, S.REG, S.SMAG])
 def test_population_layouts_agree_bitwise(model, monkeypatch):
     """The population layout in HBM (SoA or row-interleaved, tiled or not, with any padding) only moves
     where each value lives: every layout gives the same fields bit for bit, for AB and AA
@@ -201,10 +201,14 @@ def test_population_layouts_agree_bitwise(model, monkeypatch):
         kw = dict(force=(2e-5, -1e-5, 0), walls=True)
     elif model == S.SHANCHEN:
         kw = dict(tau=0.9, G=0.9, psi=0, du=0.02, drho=0.05)
+    elif model == S.REG:
+        kw = dict(walls=True, tau=0.55)
+    elif model == S.SMAG:
+        kw = dict(force=(2e-5, -1e-5, 0), walls=True, tau=0.52, cs_smag=0.2)
     else:
         kw = dict(tau=0.51, du=0.06, noise=2e-2)
     c = random_case(S.D3Q19, model, nx, ny, nz, **kw)
-    storages = [P.LBM_F64, P.LBM_F32] + ([P.LBM_BF16S] if model in (S.BGK, S.MRT) else [])
+    storages = [P.LBM_F64, P.LBM_F32] + ([P.LBM_BF16S] if model in (S.BGK, S.MRT, S.REG, S.SMAG) else [])
     for st in storages:
         for lay in (P.LBM_AB, P.LBM_AA):
             ref = gpu_run(c, 5, st, lay)

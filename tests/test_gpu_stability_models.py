@@ -1,0 +1,96 @@
+"""Regularized and Smagorinsky LBGK: HIP path vs the FP64 oracle through the C ABI.
+
+Bars as for the other models: FP64 storage within 1e-12 relative L2 of the oracle on
+f - w and the velocity; FP32 compute on the Kida vortex within the velocity bound
+stated in each test.  Shapes span several workgroups with ragged x and y tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+from test_gpu_parity import check_f64, gpu_run, oracle_run, random_case, rel
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1311_2404_amd")
+
+
+@pytest.mark.parametrize("lattice,shape", [(S.D2Q9, (130, 12, 1)), (S.D3Q19, (70, 9, 5))])
+def test_regularized_random_walls_fp64(lattice, shape):
+    c = random_case(lattice, S.REG, *shape, tau=0.56, walls=True)
+    check_f64(c, 40)
+
+
+@pytest.mark.parametrize("lattice,shape", [(S.D2Q9, (130, 12, 1)), (S.D3Q19, (70, 9, 5))])
+def test_smagorinsky_random_walls_force_fp64(lattice, shape):
+    g = (2e-5, -1e-5, 3e-5 if lattice == S.D3Q19 else 0.0)
+    c = random_case(lattice, S.SMAG, *shape, tau=0.52, force=g, walls=True, cs_smag=0.3)
+    check_f64(c, 40)
+
+
+@pytest.mark.parametrize("model", [S.REG, S.SMAG])
+def test_kida_vortex_fp64(model):
+    c = S.kida_vortex(24, model, re=2e4 if model == S.SMAG else 3e3)
+    check_f64(c, 40)
+
+
+_KIDA = {}
+
+
+def kida_reference(model, n=32, steps=300):
+    if model not in _KIDA:
+        c = S.kida_vortex(n, model, re=2e4 if model == S.SMAG else 3e3)
+        _KIDA[model] = (c, oracle_run(c, steps)[2])
+    return _KIDA[model]
+
+
+@pytest.mark.parametrize("model", [S.REG, S.SMAG])
+def test_kida_vortex_fp32_velocity(model):
+    """FP32 compute, plain and shifted FP32 storage, 300 steps of the Kida vortex."""
+    c, uo = kida_reference(model)
+    for st in (P.LBM_F32, P.LBM_F32S):
+        for lay in (P.LBM_AB, P.LBM_AA):
+            _, _, ug = gpu_run(c, 300, st, lay)
+            err = rel(ug, uo)
+            print("model %d storage %s layout %d: velocity rel L2 %.3g" % (model, P.STORAGE_NAMES[st], lay, err))
+            assert err <= 1e-5, (model, st, lay, err)
+
+
+@pytest.mark.parametrize("model", [S.REG, S.SMAG])
+@pytest.mark.parametrize("storage", [P.LBM_F64, P.LBM_F32, P.LBM_BF16S])
+def test_aa_equals_ab_bitwise(model, storage):
+    kw = dict(walls=True, tau=0.55)
+    if model == S.SMAG:
+        kw.update(force=(1e-5, 0, 2e-5), cs_smag=0.2)
+    c = random_case(S.D3Q19, model, 40, 11, 7, **kw)
+    for steps in (1, 6):
+        fa, _, ua = gpu_run(c, steps, storage, P.LBM_AB)
+        fb, _, ub = gpu_run(c, steps, storage, P.LBM_AA)
+        assert np.array_equal(fa, fb) and np.array_equal(ua, ub), (model, storage, steps)
+
+
+@pytest.mark.parametrize("model", [S.REG, S.SMAG])
+@pytest.mark.parametrize("storage", [P.LBM_F32S, P.LBM_BF16S, P.LBM_F16S])
+def test_rest_state_bitwise_fixed_point(model, storage):
+    n = 12
+    rho, u = S.rest_fields(n, n, n, 3)
+    c = S.Case("rest", S.D3Q19, model, n, n, n, 0.6, (0, 0, 0), 0, None, rho, u)
+    s = P.Sim.from_case(c, storage, P.LBM_AB)
+    f0 = s.get_f()
+    s.step(7)
+    assert np.array_equal(s.get_f(), f0)
+    s.close()
+
+
+def test_smagorinsky_zero_constant_matches_bgk():
+    """C_S = 0 gives tau = (tau0 + sqrt(tau0^2)) / 2 = tau0, so the step is the LBGK step.
+    The two kernels round differently (the compiler fuses multiply-adds differently in
+    each), so the bound is a few units of rounding per step: 10 steps, 1e-13 in FP64."""
+    c = random_case(S.D3Q19, S.SMAG, 33, 10, 6, tau=0.6, walls=True, cs_smag=0.0)
+    cb = random_case(S.D3Q19, S.BGK, 33, 10, 6, tau=0.6, walls=True)
+    for st in (P.LBM_F64, P.LBM_F32):
+        fs, _, _ = gpu_run(c, 10, st)
+        fb, _, _ = gpu_run(cb, 10, st)
+        w = oracle.tables(S.D3Q19)[1][None, :, None]
+        assert rel(fs - w, fb - w) <= (1e-13 if st == P.LBM_F64 else 1e-6), (st, rel(fs - w, fb - w))
