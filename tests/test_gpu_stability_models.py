@@ -86,11 +86,14 @@ def test_rest_state_bitwise_fixed_point(model, storage):
 def test_smagorinsky_zero_constant_matches_bgk():
     """C_S = 0 gives tau = (tau0 + sqrt(tau0^2)) / 2 = tau0, so the step is the LBGK step.
     The two kernels round differently (the compiler fuses multiply-adds differently in
-    each), so the bound is a few units of rounding per step: 10 steps, 1e-13 in FP64."""
+    each), so the bound is a few units of rounding per step: 10 steps, 1e-13 in FP64.
+    Plain FP32 storage holds f ~ 0.05, whose unit in the last place (4e-9) is ~4e-6 of
+    the deviation f - w ~ 1e-3 compared here, so one-ulp differences already show as
+    1e-6 relative: the FP32 bound is 1e-5."""
     c = random_case(S.D3Q19, S.SMAG, 33, 10, 6, tau=0.6, walls=True, cs_smag=0.0)
     cb = random_case(S.D3Q19, S.BGK, 33, 10, 6, tau=0.6, walls=True)
     for st in (P.LBM_F64, P.LBM_F32):
         fs, _, _ = gpu_run(c, 10, st)
         fb, _, _ = gpu_run(cb, 10, st)
         w = oracle.tables(S.D3Q19)[1][None, :, None]
-        assert rel(fs - w, fb - w) <= (1e-13 if st == P.LBM_F64 else 1e-6), (st, rel(fs - w, fb - w))
+        assert rel(fs - w, fb - w) <= (1e-13 if st == P.LBM_F64 else 1e-5), (st, rel(fs - w, fb - w))
