@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("g", C.c_double * 3), ("s", C.c_double * 19),
                 ("alpha_init", C.c_int), ("alpha_tol", C.c_double), ("alpha_maxit", C.c_int),
                 ("mlp", C.POINTER(C.c_double)), ("G", C.c_double), ("psi", C.c_int),
-                ("cs_smag", C.c_double)]
+                ("cs_smag", C.c_double), ("u_bc", C.c_double * 3)]
 
 
 class Stats(C.Structure):
@@ -174,7 +174,8 @@ class Oracle:
     """One simulation held by the oracle: parameters plus the population array."""
 
     def __init__(self, lattice, model, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), mrt_rates=None,
-                 alpha_init=0, alpha_tol=1e-10, alpha_maxit=20, mlp=None, G=0.0, psi=0, cs_smag=0.1):
+                 alpha_init=0, alpha_tol=1e-10, alpha_maxit=20, mlp=None, G=0.0, psi=0, cs_smag=0.1,
+                 u_bc=(0.0, 0.0, 0.0)):
         self.p = Params()
         self.p.lattice, self.p.model = lattice, model
         self.p.nx, self.p.ny, self.p.nz = nx, ny, nz
@@ -189,6 +190,8 @@ class Oracle:
         self.p.mlp = _dp(self._mlp) if mlp is not None else None
         self.p.G, self.p.psi = G, psi
         self.p.cs_smag = cs_smag
+        for a in range(3):
+            self.p.u_bc[a] = float(u_bc[a]) if a < len(u_bc) else 0.0
         self.q = q_of(lattice)
         self.n = nx * ny * nz
         self.ncomp = 2 if model == SHANCHEN else 1
@@ -199,6 +202,7 @@ class Oracle:
     @classmethod
     def from_case(cls, case, **kw):
         kw.setdefault("cs_smag", case.cs_smag)
+        kw.setdefault("u_bc", case.u_bc)
         o = cls(case.lattice, case.model, case.nx, case.ny, case.nz, case.tau, case.force,
                 case.mrt_rates, G=case.G, psi=case.psi, **kw)
         if case.flags is not None:

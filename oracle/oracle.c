@@ -34,6 +34,11 @@
  *    projection would drop the -F/2 first moment that Guo forcing relies on).
  *  - Smagorinsky model: Q from the polynomial equilibrium at the force-shifted
  *    velocity, and the Guo prefactor 1 - 1/(2 tau) with the local tau = tau0 + tau_t.
+ *  - Equilibrium velocity nodes (flag 2): a population is missing when the node it
+ *    streams from is a wall node; it takes the value of the opposite population at the
+ *    node; rho is summed after that; the node's post-collision state is the polynomial
+ *    feq(rho, u_bc), with no relaxation and no force.  The macroscopic output of such
+ *    a node is that rho and u_bc.  Single-component polynomial-equilibrium models only.
  */
 #include "oracle.h"
 
@@ -708,6 +713,20 @@ static void sc_force(const orc_params *P, const lattice_t *L, const double *psi,
     for (int a = 0; a < 3; a++) F[a] = -P->G * psi[c * N + n] * s[a] + rho_c * P->g[a];
 }
 
+/* Equilibrium velocity node (boundary conditions subsection): the populations that
+ * stream in from wall nodes are missing and are replaced by the opposite population of
+ * the same node (bounce-back); returns drho = sum of the completed set (as h). */
+static double velocity_node_drho(const orc_params *P, const lattice_t *L, const uint8_t *flags, int64_t x,
+                                 int64_t y, int64_t z, const double *h) {
+    double drho = 0.0;
+    for (int i = 0; i < L->q; i++) {
+        int back[3] = {-L->e[i][0], -L->e[i][1], -L->e[i][2]};
+        int missing = flags[neighbour(P, x, y, z, back)] == 1;
+        drho += missing ? h[L->opp[i]] : h[i];
+    }
+    return drho;
+}
+
 int orc_init_eq(const orc_params *P, const double *rho, const double *u, const double *df, double *f) {
     if (check_params(P)) return -1;
     lattice_t L;
@@ -743,6 +762,9 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
     if (C == 2 && flags)
         for (int64_t n = 0; n < N; n++)
             if (flags[n]) return -2; /* walls are not defined for the two-component model */
+    if (flags)
+        for (int64_t n = 0; n < N; n++)
+            if (flags[n] > 2 || (flags[n] == 2 && P->model == ORC_ELBM)) return -2;
     double *cur = (double *)malloc(sizeof(double) * C * q * N);
     double *nxt = (double *)malloc(sizeof(double) * C * q * N);
     double *psi = C == 2 ? (double *)malloc(sizeof(double) * 2 * N) : NULL;
@@ -778,6 +800,9 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
                  * opposite direction instead of colliding (w_i = w_opp(i), so the same on h) */
                 for (int c = 0; c < C; c++)
                     for (int i = 0; i < q; i++) post[c][i] = hl[c][L.opp[i]];
+            } else if (flags && flags[n] == 2) {
+                double drho = velocity_node_drho(P, &L, flags, x, y, z, hl[0]);
+                heq_poly(&L, drho, P->u_bc, post[0]);
             } else if (C == 1) {
                 node_info info = {0, 1};
                 collide_single(P, &L, hl[0], post[0], &info);
@@ -860,7 +885,11 @@ int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double
             rho[c * N + n] = rc[c];
         }
         double v[3] = {0, 0, 0};
-        if (!(flags && flags[n] == 1)) {
+        if (flags && flags[n] == 2 && C == 1) {
+            for (int i = 0; i < q; i++) hl[i] = f[(int64_t)i * N + n] - L.w[i];
+            rho[n] = 1.0 + velocity_node_drho(P, &L, flags, x, y, z, hl);
+            for (int a = 0; a < 3; a++) v[a] = P->u_bc[a];
+        } else if (!(flags && flags[n] == 1)) {
             if (C == 1) {
                 double gfac = P->model == ORC_ELBM ? 0.0 : 0.5;
                 for (int a = 0; a < 3; a++) v[a] = (jc[0][a] + gfac * rc[0] * P->g[a]) / rc[0];

@@ -14,7 +14,8 @@
  *          17 (0,1,-1) 18 (0,-1,1)
  *
  * Array layouts: populations f[C][Q][N], N = nx*ny*nz with x fastest
- * (node n = x + nx*(y + ny*z)); flags[N] (0 fluid, 1 full-way bounce-back wall);
+ * (node n = x + nx*(y + ny*z)); flags[N] (0 fluid, 1 full-way bounce-back wall,
+ * 2 equilibrium velocity node with the velocity u_bc);
  * densities rho[C][N]; velocities u[3][N] (the z row is zero on D2Q9).
  *
  * Parity unpinned (no printed values in the paper): the MRT, ELBM,
@@ -45,6 +46,7 @@ typedef struct {
     double G;             /* Shan-Chen coupling */
     int psi;              /* 0: psi = rho, 1: psi = 1 - exp(-rho) */
     double cs_smag;       /* Smagorinsky constant C_S (ORC_SMAG) */
+    double u_bc[3];       /* velocity of the equilibrium velocity nodes (flag 2) */
 } orc_params;
 
 typedef struct {

@@ -64,7 +64,7 @@ def uniform_pm(seed: int, stream: int, shape, amp: float, dtype=np.float64) -> n
 # lattice identifiers shared with the C ABI (plain integers, no tables)
 D2Q9, D3Q19 = 0, 1
 BGK, MRT, ELBM, SHANCHEN, REG, SMAG = 0, 1, 2, 3, 4, 5
-FLUID, WALL = 0, 1
+FLUID, WALL, VELOCITY = 0, 1, 2
 Q_OF = {D2Q9: 9, D3Q19: 19}
 D_OF = {D2Q9: 2, D3Q19: 3}
 
@@ -94,6 +94,7 @@ class Case:
     G: float = 0.0
     psi: int = 0
     cs_smag: float = 0.1
+    u_bc: tuple = (0.0, 0.0, 0.0)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -167,6 +168,27 @@ def taylor_green_2d(nx, ny, u0):
     u[0] = -u0 * np.cos(kx * x) * np.sin(ky * y)
     u[1] = u0 * np.sin(kx * x) * np.cos(ky * y)
     return np.ones((1, x.size)), u
+
+
+def cavity_flags(nx, ny, nz):
+    """Lid-driven cavity: walls on x = nx-1, y = 0, y = ny-1, z = 0, z = nz-1; the lid
+    is the rest of the plane x = 0 (velocity nodes)."""
+    fl = np.zeros((nz, ny, nx), dtype=np.uint8)
+    fl[:, :, 0] = VELOCITY
+    fl[:, :, nx - 1] = WALL
+    fl[:, 0, :] = WALL
+    fl[:, ny - 1, :] = WALL
+    fl[0, :, :] = WALL
+    fl[nz - 1, :, :] = WALL
+    return fl
+
+
+def couette_flags(nx, ny, nz):
+    """Plane Couette cell: velocity nodes on x = 0, walls on x = nx-1, periodic in y, z."""
+    fl = np.zeros((nz, ny, nx), dtype=np.uint8)
+    fl[:, :, 0] = VELOCITY
+    fl[:, :, nx - 1] = WALL
+    return fl
 
 
 def kida_3d(n, u0):
@@ -250,6 +272,18 @@ def kida_vortex(n=256, model=SMAG, re=1.28e5, u0=0.05, steps=1000, cs_smag=0.1):
     nu = n * u0 / re
     return Case("d3q19_kida_%d_re%g" % (n, re), D3Q19, model, n, n, n, tau_from_nu(nu), (0.0, 0.0, 0.0),
                 steps, None, rho, u, cs_smag=cs_smag, extra={"u0": u0, "nu": nu, "re": re})
+
+
+def lid_driven_cavity(n=254, model=BGK, re=1000.0, u_lid=0.05, steps=1000, mrt_s_other=1.2, cs_smag=0.1):
+    """D3Q19 lid-driven cavity on an n^3 lattice (the paper's single-fluid benchmark
+    case): full-way bounce-back walls, an equilibrium-velocity lid on x = 0 moving along
+    y at u_lid, Re = u_lid (n - 2) / nu, fluid at rest."""
+    rho, u = rest_fields(n, n, n, 3)
+    tau = tau_from_nu(u_lid * (n - 2) / re)
+    rates = mrt_rates_d3q19(1 / tau, mrt_s_other) if model == MRT else None
+    return Case("d3q19_ldc_%d_re%g" % (n, re), D3Q19, model, n, n, n, tau, (0.0, 0.0, 0.0), steps,
+                cavity_flags(n, n, n), rho, u, mrt_rates=rates, cs_smag=cs_smag, u_bc=(0.0, u_lid, 0.0),
+                extra={"re": re, "u_lid": u_lid})
 
 
 def c5_shan_chen(n=384, steps=2000, G=0.9, amp=0.01, seed=DEFAULT_SEED, tau=1.0):

@@ -807,3 +807,139 @@ def test_kida_initial_field():
     np.testing.assert_array_equal(uy, ux.transpose(1, 2, 0))
     np.testing.assert_array_equal(uz, uy.transpose(1, 2, 0))
     assert np.abs(ux).max() > 0.1 * u0
+
+
+# --------------------------------------------------------------------------- equilibrium velocity nodes
+
+def _steady_couette(nx, tau, U, model=S.BGK, **kw):
+    ny = nz = 4
+    rho, u = S.rest_fields(nx, ny, nz, 3)
+    o = oracle.Oracle(S.D3Q19, model, nx, ny, nz, tau, u_bc=(0.0, U, 0.0), **kw)
+    o.set_flags(S.couette_flags(nx, ny, nz))
+    o.init_eq(rho, u)
+    prev = None
+    for _ in range(200):
+        o.run(500)
+        r, v = o.macro()
+        uy = v[1].reshape(nz, ny, nx)[0, 0].copy()
+        if prev is not None and np.abs(uy - prev).max() < 1e-17:
+            break
+        prev = uy
+    return o, r, v
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0, 1.3])
+def test_couette_equilibrium_lid_closed_form(tau):
+    """Plane Couette flow between an equilibrium-velocity lid (x = 0) and a bounce-back
+    wall (x = nx - 1).  At steady state the profile is linear, u_y = a (x_w - x), with
+    (i) the bounce-back wall halfway to the wall node, x_w = nx - 1.5, and (ii) the lid
+    emitting feq(U) where the bulk post-collision state is feq(u) - 3 (tau - 1) w e_x e_y u':
+    matching the part linear in u gives u(0) = U + (tau - 1) u'.  Together
+    u_y(x) = U (nx - 1.5 - x) / (nx - 2.5 + tau); at tau = 1 the lid sits on its node."""
+    nx, U = 12, 0.05
+    _, r, v = _steady_couette(nx, tau, U)
+    uy = v[1].reshape(4, 4, nx)
+    x = np.arange(1, nx - 1)
+    exact = U * (nx - 1.5 - x) / (nx - 2.5 + tau)
+    np.testing.assert_allclose(uy[:, :, 1:nx - 1], np.broadcast_to(exact, (4, 4, nx - 2)), rtol=1e-12, atol=0)
+    assert np.abs(uy[:, :, 0] - U).max() == 0.0          # the lid reports its velocity
+    assert np.abs(v[0]).max() < 1e-15 and np.abs(v[2]).max() < 1e-15
+    assert np.abs(r - 1.0).max() < 1e-14
+
+
+@pytest.mark.parametrize("model", [S.MRT, S.REG])
+def test_couette_lid_tau_one_other_models(model):
+    """At tau = 1 (MRT with every rate 1) the profile passes through (0, U) for these
+    models too: the lid emits feq(U), which is the bulk's post-collision state there."""
+    nx, U = 10, 0.04
+    kw = dict(mrt_rates=np.ones(19)) if model == S.MRT else {}
+    _, _, v = _steady_couette(nx, 1.0, U, model, **kw)
+    x = np.arange(1, nx - 1)
+    np.testing.assert_allclose(v[1].reshape(4, 4, nx)[0, 0, 1:nx - 1], U * (nx - 1.5 - x) / (nx - 1.5),
+                               rtol=1e-12, atol=0)
+
+
+def test_velocity_node_first_step():
+    """From rest, after one step the fluid nodes next to the lid hold feq(1, U) in every
+    population that streamed from the lid (e_x = +1) and w_i elsewhere."""
+    n, U = 10, (0.0, 0.05, 0.0)
+    c = S.lid_driven_cavity(n, S.BGK, re=100.0, u_lid=U[1])
+    o = oracle.Oracle.from_case(c)
+    o.run(1)
+    e, w, _ = oracle.tables(S.D3Q19)
+    fe = oracle.feq(S.D3Q19, 1.0, U)
+    f = o.f[0].reshape(19, n, n, n)  # [q][z][y][x]
+    for z in range(3, n - 3):
+        for y in range(3, n - 3):
+            for i in range(19):
+                want = fe[i] if e[i, 0] == 1 else w[i]
+                assert abs(f[i, z, y, 1] - want) <= 1e-16
+
+
+def test_cavity_mirror_symmetry_and_rest():
+    """The cavity is symmetric under z -> nz - 1 - z: u_x, u_y even, u_z odd.  With a
+    lid at rest, the rest state is a fixed point."""
+    n = 12
+    c = S.lid_driven_cavity(n, S.BGK, re=50.0)
+    o = oracle.Oracle.from_case(c)
+    o.run(60)
+    _, v = o.macro()
+    V = v.reshape(3, n, n, n)
+    # equal up to the rounding of the mirrored summation order (velocities <= 0.05)
+    np.testing.assert_allclose(V[0], V[0][::-1], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(V[1], V[1][::-1], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(V[2], -V[2][::-1], rtol=0, atol=1e-15)
+    assert np.abs(V[2]).max() > 1e-6 and np.abs(V[0]).max() > 1e-5
+    c0 = S.lid_driven_cavity(n, S.BGK, re=50.0)
+    c0.u_bc = (0.0, 0.0, 0.0)
+    o0 = oracle.Oracle.from_case(c0)
+    f0 = o0.f.copy()
+    o0.run(10)
+    assert np.abs(o0.f - f0).max() <= 2e-16
+
+
+def test_velocity_nodes_not_for_entropic_or_two_component():
+    n = 6
+    c = S.lid_driven_cavity(n, S.BGK)
+    o = oracle.Oracle(S.D3Q19, S.ELBM, n, n, n, 0.6)
+    o.set_flags(c.flags)
+    o.init_eq(c.rho, c.u)
+    with pytest.raises(ValueError):
+        o.run(1)
+
+
+def test_velocity_node_rule_on_random_state():
+    """One step from a random state, the rule applied by hand at every lid node: the
+    populations streamed from wall nodes are missing and take the value of the
+    opposite population of the node; rho sums the completed set; feq(rho, u_lid) leaves
+    along every e_i and arrives at x + e_i.  The macroscopic output reports that rho."""
+    n, U = 8, (0.0, 0.05, 0.0)
+    c = S.lid_driven_cavity(n, S.BGK, re=100.0, u_lid=U[1])
+    o = oracle.Oracle.from_case(c)
+    e, w, opp = oracle.tables(S.D3Q19)
+    rng = np.random.default_rng(31)
+    f0 = w[:, None] * (1 + 0.2 * (2 * rng.random((19, n ** 3)) - 1))
+    o.set_f(f0[None])
+    flags = c.flags.reshape(n, n, n)  # [z][y][x]
+    rho_out, _ = o.macro()
+    o.run(1)
+    f1 = o.f[0].reshape(19, n, n, n)
+    F0 = f0.reshape(19, n, n, n)
+    checked = 0
+    for z in range(n):
+        for y in range(n):
+            for x in range(n):
+                if flags[z, y, x] != S.VELOCITY:
+                    continue
+                comp = np.empty(19)
+                for i in range(19):
+                    src = flags[(z - e[i, 2]) % n, (y - e[i, 1]) % n, (x - e[i, 0]) % n]
+                    comp[i] = F0[opp[i], z, y, x] if src == S.WALL else F0[i, z, y, x]
+                rho = comp.sum()
+                assert abs(rho_out[0].reshape(n, n, n)[z, y, x] - rho) <= 2e-15
+                fe = oracle.feq(S.D3Q19, rho, U)
+                for i in range(19):
+                    dst = f1[i, (z + e[i, 2]) % n, (y + e[i, 1]) % n, (x + e[i, 0]) % n]
+                    assert abs(dst - fe[i]) <= 4e-16, (x, y, z, i)
+                checked += 1
+    assert checked == (n - 2) ** 2
