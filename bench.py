@@ -179,6 +179,22 @@ def run_extras(P, S, stream, torch):
                                 "nonfinite_nodes": int(d[6])}
     out["d3q19_kida_256_fp32"] = kida
     print("[bench] Kida done", file=sys.stderr, flush=True)
+
+    # D3Q19 lid-driven cavity 254^3 at Re 1000, FP32 storage, AB: full-way bounce-back
+    # walls and an equilibrium-velocity lid (u = 0.05), for each model that takes it
+    ldc = {}
+    for model, name in [(S.BGK, "bgk"), (S.MRT, "mrt"), (S.REG, "regularized"), (S.SMAG, "smagorinsky")]:
+        cl = S.lid_driven_cavity(254, model, re=1000.0)
+        s = P.Sim.from_case(cl, P.LBM_F32, P.LBM_AB, stream=stream)
+        s.step(20)
+        ms = _time_steps(s, stream, torch, 200)
+        d = s.diag()
+        s.close()
+        ldc[name] = {"mlups": round(cl.n / ms / 1e3, 1), "ms_per_step": round(ms, 4), "bytes_per_node": 153,
+                     "hbm_gbs_algorithmic": round(153 * cl.n / (ms * 1e-3) / 1e9, 1), "tau": round(cl.tau, 6),
+                     "ke_after_220_steps": float(d[5]), "nonfinite_nodes": int(d[6])}
+    out["d3q19_ldc_254_re1000_fp32"] = ldc
+    print("[bench] cavity done", file=sys.stderr, flush=True)
     return out
 
 

@@ -57,7 +57,12 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_BF16S = 3, LBM_F16S = 4 };
 /* Streaming pattern (GPU-algorithms subsection): AB = two copies, ping-pong;
  * AA = one copy updated in place, even and odd steps access different slots. */
 enum { LBM_AB = 0, LBM_AA = 1 };
-enum { LBM_FLUID = 0, LBM_WALL_BB = 1 }; /* uint8 node flags */
+/* uint8 node flags: fluid; full-way bounce-back wall (a dry node that returns what it
+ * receives, boundary-conditions subsection); equilibrium velocity node (a fluid node on
+ * a domain face whose populations streamed in from wall nodes are missing: each takes
+ * the value of its opposite at the node, rho is summed over the completed set, and the
+ * node leaves feq(rho, u_bc), the equilibrium approach of the same subsection). */
+enum { LBM_FLUID = 0, LBM_WALL_BB = 1, LBM_VELOCITY = 2 };
 enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,      /* invalid argument */
@@ -98,6 +103,12 @@ int lbm_set_elbm(lbm_sim *sim, int alpha_init, double tol, int max_iter);
  * 1: 1 - exp(-rho)).  Default G = 0, psi = 0. */
 int lbm_set_shanchen(lbm_sim *sim, double G, int psi);
 
+/* Velocity u[3] of every LBM_VELOCITY node (u[2] ignored on D2Q9); default 0.  The
+ * macroscopic output of such a node is the density of its completed set and this
+ * velocity.  Velocity nodes are accepted by lbm_set_flags for LBM_BGK, LBM_MRT,
+ * LBM_REGULARIZED and LBM_SMAGORINSKY. */
+int lbm_set_velocity_bc(lbm_sim *sim, const double u[3]);
+
 /* Smagorinsky constant C_S >= 0 of the LBM_SMAGORINSKY model (subgrid-model
  * subsection): tau_t = (sqrt(tau0^2 + 4 cs^-4 C_S^2 |Q|) - tau0)/2 with
  * Q_ab = sum_i e_ia e_ib (f_i - feq_i), |Q| = (Q_ab Q_ab)^(1/2), tau = tau0 + tau_t, and the
@@ -109,8 +120,9 @@ int lbm_set_smagorinsky(lbm_sim *sim, double cs);
  * NULL = the null stream. */
 int lbm_set_stream(lbm_sim *sim, void *hip_stream);
 
-/* Node flags, host array uint8[N] (LBM_FLUID / LBM_WALL_BB), copied.  Before or after
- * init.  Walls are not supported with LBM_SHANCHEN (LBM_EUNSUPPORTED). */
+/* Node flags, host array uint8[N] (LBM_FLUID / LBM_WALL_BB / LBM_VELOCITY), copied.
+ * Before or after init.  Values above 2: LBM_EINVAL.  Walls are not supported with
+ * LBM_SHANCHEN, velocity nodes not with LBM_SHANCHEN or LBM_ELBM (LBM_EUNSUPPORTED). */
 int lbm_set_flags(lbm_sim *sim, const uint8_t *flags);
 
 /* Initialise f = f_eq(rho, u) (the entropic equilibrium for ELBM, else the polynomial

@@ -21,7 +21,7 @@ LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_BGK, LBM_MRT, LBM_ELBM, LBM_SHANCHEN, LBM_REGULARIZED, LBM_SMAGORINSKY = 0, 1, 2, 3, 4, 5
 LBM_F64, LBM_F32, LBM_F32S, LBM_BF16S, LBM_F16S = 0, 1, 2, 3, 4
 LBM_AB, LBM_AA = 0, 1
-LBM_FLUID, LBM_WALL_BB = 0, 1
+LBM_FLUID, LBM_WALL_BB, LBM_VELOCITY = 0, 1, 2
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSUPPORTED, LBM_EDIVERGED = 0, -1, -2, -3, -4, -5, -6
 MLP_NPARAM = 1313
 MLP_NTOTAL = 1325  # weights + input normalisation mu[6], isd[6]
@@ -36,6 +36,7 @@ _SIGS = [
     ("lbm_set_mrt_rates", C.c_int, [_vp, _dp, C.c_int]),
     ("lbm_set_elbm", C.c_int, [_vp, C.c_int, C.c_double, C.c_int]),
     ("lbm_set_shanchen", C.c_int, [_vp, C.c_double, C.c_int]),
+    ("lbm_set_velocity_bc", C.c_int, [_vp, _dp]),
     ("lbm_set_smagorinsky", C.c_int, [_vp, C.c_double]),
     ("lbm_set_stream", C.c_int, [_vp, _vp]),
     ("lbm_set_flags", C.c_int, [_vp, C.POINTER(C.c_uint8)]),
@@ -136,6 +137,11 @@ def lbm_set_elbm(sim, alpha_init=0, tol=1e-10, max_iter=20):
 
 def lbm_set_shanchen(sim, G, psi=0):
     _err(sim, lib().lbm_set_shanchen(sim, G, psi))
+
+
+def lbm_set_velocity_bc(sim, u):
+    u = _host64(list(u) + [0.0] * (3 - len(u)))
+    _err(sim, lib().lbm_set_velocity_bc(sim, _d(u)))
 
 
 def lbm_set_smagorinsky(sim, cs):
@@ -307,6 +313,8 @@ class Sim:
             lbm_set_smagorinsky(s.h, case.cs_smag)
         if case.flags is not None:
             lbm_set_flags(s.h, case.flags)
+        if any(case.u_bc):
+            lbm_set_velocity_bc(s.h, case.u_bc)
         if init:
             s.init_eq(case.rho, case.u, case.df)
         return s

@@ -33,6 +33,7 @@ struct lbm_sim {
     double G = 0.0;
     int psi_mode = 0;
     double cs_smag = 0.1;  // Smagorinsky constant
+    double u_bc[3] = {0.0, 0.0, 0.0};  // velocity of the equilibrium velocity nodes
     hipStream_t stream = nullptr;
     int device = 0;
     void *buf[2] = {nullptr, nullptr};
@@ -138,6 +139,7 @@ StepParams base_params(const lbm_sim *s) {
     for (int a = 0; a < 3; a++) p.g[a] = s->g[a];
     p.has_force = (s->g[0] != 0.0 || s->g[1] != 0.0 || s->g[2] != 0.0) ? 1 : 0;
     for (int k = 0; k < 19; k++) p.s[k] = s->s[k];
+    for (int a = 0; a < 3; a++) p.u_bc[a] = s->u_bc[a];
     p.tau0 = s->tau;
     p.smag_k = 36.0 * s->cs_smag * s->cs_smag;
     p.beta = 0.5 / s->tau;
@@ -282,6 +284,7 @@ int macro_into(lbm_sim *s, void *rho, void *u, int fp64, unsigned int *bad) {
     m.psi = s->psi_d;
     m.G = s->G;
     for (int a = 0; a < 3; a++) m.g[a] = s->g[a];
+    for (int a = 0; a < 3; a++) m.u_bc[a] = s->u_bc[a];
     m.rho_out = rho;
     m.u_out = u;
     m.fp64 = fp64;
@@ -381,6 +384,16 @@ int lbm_set_shanchen(lbm_sim *s, double G, int psi) {
     return LBM_OK;
 }
 
+int lbm_set_velocity_bc(lbm_sim *s, const double *u) {
+    if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
+    if (!u) return fail(s, LBM_EINVAL, "u is NULL");
+    double v[3] = {u[0], u[1], s->D == 3 ? u[2] : 0.0};
+    for (int a = 0; a < 3; a++)
+        if (!std::isfinite(v[a])) return fail(s, LBM_EINVAL, "the velocity must be finite");
+    for (int a = 0; a < 3; a++) s->u_bc[a] = v[a];
+    return LBM_OK;
+}
+
 int lbm_set_smagorinsky(lbm_sim *s, double cs) {
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
     if (s->model != LBM_SMAGORINSKY) return fail(s, LBM_EUNSUPPORTED, "the constant belongs to the Smagorinsky model");
@@ -398,13 +411,16 @@ int lbm_set_stream(lbm_sim *s, void *stream) {
 int lbm_set_flags(lbm_sim *s, const uint8_t *flags) {
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
     if (!flags) return fail(s, LBM_EINVAL, "flags is NULL");
-    bool walls = false;
+    bool walls = false, vel = false;
     for (uint32_t n = 0; n < s->N; n++) {
-        if (flags[n] > LBM_WALL_BB) return fail(s, LBM_EINVAL, "flag values must be 0 or 1");
-        walls = walls || flags[n] == LBM_WALL_BB;
+        if (flags[n] > LBM_VELOCITY) return fail(s, LBM_EINVAL, "flag values must be 0, 1 or 2");
+        walls = walls || flags[n] != LBM_FLUID;
+        vel = vel || flags[n] == LBM_VELOCITY;
     }
     if (walls && s->model == LBM_SHANCHEN)
         return fail(s, LBM_EUNSUPPORTED, "walls are not supported with the Shan-Chen model");
+    if (vel && s->model == LBM_ELBM)
+        return fail(s, LBM_EUNSUPPORTED, "velocity nodes are built for the polynomial-equilibrium models");
     HIPCHK(s, hipSetDevice(s->device));
     if (!s->flags_d) HIPCHK(s, hipMalloc(&s->flags_d, s->N));
     HIPCHK(s, hipMemcpyAsync(s->flags_d, flags, s->N, hipMemcpyHostToDevice, s->stream));

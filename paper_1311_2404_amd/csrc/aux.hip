@@ -111,6 +111,8 @@ __global__ void k_set_plane(PlaneParams p) {
 
 // Macroscopic output.  Density per component; velocity (j + F/2)/rho for the forced
 // single-component models, j/rho for ELBM, the mixture velocity for Shan-Chen; 0 on walls.
+// Equilibrium velocity nodes report the density of their completed population set (the
+// populations streamed from walls replaced by their opposites) and the prescribed velocity.
 template <class L, class St>
 __global__ void k_macro(MacroParams p) {
     using T = typename St::T;
@@ -119,6 +121,8 @@ __global__ void k_macro(MacroParams p) {
     if (n >= p.N) return;
     const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
+    const uint32_t fl = p.flags ? p.flags[n] : 0u;
+    const bool vel = fl == 2u && p.ncomp == 1;
     for (int c = 0; c < p.ncomp; c++) {
         const T *pop = static_cast<const T *>(p.pop) + size_t(c) * L::Q * p.S;
         C h[L::Q];
@@ -131,14 +135,24 @@ __global__ void k_macro(MacroParams p) {
         }
         const Macro<C> m = moments<L, C>(h);
         rho[c] = double(m.rho);
+        if (vel) {
+            C dr = C(0);
+#pragma unroll
+            for (int i = 0; i < L::Q; i++)
+                dr += p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1 ? h[opp(i)] : h[i];
+            rho[c] = double(C(1) + dr);
+        }
         j[0] += double(m.jx);
         j[1] += double(m.jy);
         j[2] += double(m.jz);
     }
     const double rt = rho[0] + rho[1];
     double v[3] = {0.0, 0.0, 0.0};
-    const bool wall = p.flags && p.flags[n] == 1;
-    if (!wall) {
+    const bool wall = fl == 1u;
+    if (vel) {
+        for (int k = 0; k < 3; k++) v[k] = p.u_bc[k];
+        if (L::D == 2) v[2] = 0.0;
+    } else if (!wall) {
         if (p.model == M_SC) {
             const C *psi = static_cast<const C *>(p.psi);
             double F[3] = {0.0, 0.0, 0.0};

@@ -100,6 +100,7 @@ struct MacroParams {
     const uint8_t *flags;
     const void *psi;   // Shan-Chen pseudopotential (model == SC)
     double G, g[3];
+    double u_bc[3];    // velocity of the equilibrium velocity nodes (flag 2)
     void *rho_out, *u_out;
     int fp64;
     unsigned int *bad;  // count of non-finite / non-positive densities (or nullptr)

@@ -32,6 +32,7 @@ struct StepParams {
     double g[3];                // body acceleration
     int has_force;
     double s[19];               // MRT rates in moment order
+    double u_bc[3];             // velocity of the equilibrium velocity nodes (flag 2)
     double tau0;                // Smagorinsky: base relaxation time
     double smag_k;              // Smagorinsky: 4 cs^-4 C_S^2 = 36 C_S^2
     // entropic LBM

@@ -172,6 +172,28 @@ __device__ __forceinline__ void post_loc(int layout, int i, const Geo &g, int &s
     }
 }
 
+// Equilibrium velocity node (boundary-conditions subsection): a population that streams
+// in from a wall node is missing and takes the value of the node's opposite population;
+// rho sums the completed set; the node leaves feq(rho, u_bc) (no relaxation, no force).
+// Only nodes on a domain face run this, so the neighbour flag loads cost nothing elsewhere.
+template <class L, class C>
+__device__ __forceinline__ void velocity_node(const C *h, C *o, const StepParams &p, const Geo &g) {
+    C drho = C(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const bool missing = p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1;
+        drho += missing ? h[opp(i)] : h[i];
+    }
+    const C rho = C(1) + drho;
+    const C ux = C(p.u_bc[0]), uy = C(p.u_bc[1]), uz = C(L::D == 3 ? p.u_bc[2] : 0.0);
+    const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
+        o[i] = C(L::w(i)) * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
+    }
+}
+
 template <class L, class St, int MODEL, int LAYOUT, bool FLAGS>
 __global__ __launch_bounds__(512) void k_step(StepParams p) {
     using T = typename St::T;
@@ -218,8 +240,10 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             raw[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
         }
         T out[Q];
-        const bool wall = FLAGS && p.flags[n] == 1;
-        if (wall) {
+        const uint32_t fl = FLAGS ? p.flags[n] : 0u;
+        // equilibrium velocity nodes exist for the polynomial-equilibrium models
+        const bool vel = FLAGS && MODEL != M_ELBM && fl == 2u;
+        if (fl == 1u) {
             // full-way bounce-back: the stored values are returned along -e_i untouched
 #pragma unroll
             for (int i = 0; i < Q; i++) out[i] = raw[opp(i)];
@@ -227,7 +251,9 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             C h[Q], o[Q];
 #pragma unroll
             for (int i = 0; i < Q; i++) h[i] = St::decode(raw[i], C(L::w(i)));
-            if constexpr (MODEL == M_BGK) {
+            if (vel) {
+                velocity_node<L, C>(h, o, p, g);
+            } else if constexpr (MODEL == M_BGK) {
                 collide_bgk<L, C>(h, o, p);
             } else if constexpr (MODEL == M_MRT) {
                 collide_mrt<L, C>(h, o, p);

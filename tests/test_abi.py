@@ -125,3 +125,24 @@ def test_regularized_and_smagorinsky_arguments(lbm):
             assert ei.value.code == lbm.LBM_EINVAL
     finally:
         lbm.lbm_destroy(h)
+
+
+def test_velocity_nodes_arguments(lbm):
+    fl = np.zeros(64, np.uint8)
+    fl[:16] = lbm.LBM_VELOCITY
+    for model in (lbm.LBM_ELBM, lbm.LBM_SHANCHEN):
+        h = lbm.lbm_create(lbm.LBM_D3Q19, model, 4, 4, 4, 0.6)
+        try:
+            with pytest.raises(lbm.LbmError) as ei:
+                lbm.lbm_set_flags(h, fl)
+            assert ei.value.code == lbm.LBM_EUNSUPPORTED
+        finally:
+            lbm.lbm_destroy(h)
+    h = lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_BGK, 4, 4, 4, 0.6)
+    try:
+        lbm.lbm_set_velocity_bc(h, (0.0, 0.05, 0.0))
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_velocity_bc(h, (0.0, float("nan"), 0.0))
+        assert ei.value.code == lbm.LBM_EINVAL
+    finally:
+        lbm.lbm_destroy(h)
