@@ -76,6 +76,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("liblbm.so is not built; run `python -m paper_1311_2404_amd.build`")
+        # torch brings its own HIP runtime: let it load first, so that the library binds
+        # to the runtime torch's streams and buffers live in (loading the library before
+        # torch has ended a process with a segmentation fault)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             fn = getattr(L, name)

@@ -40,6 +40,7 @@ struct lbm_sim {
     int cur = 0;
     uint8_t *flags_d = nullptr;
     bool has_walls = false;
+    bool has_vel = false;  // some node is an equilibrium velocity node
     void *psi_d = nullptr;
     double *stage = nullptr;
     double *macro_d = nullptr;  // FP64 rho[C][N] + u[3][N] scratch for lbm_macro / lbm_diag
@@ -162,7 +163,11 @@ StepParams base_params(const lbm_sim *s) {
 //    pad of 17 such units, so that the Q population arrays do not start at addresses
 //    that differ by a large power of two (which maps the 2Q streams of a row onto the
 //    same HBM channels; measured +1 to +3% on the 256^3 step); row pitch nx.
-//  - row-interleaved, f[z][y/TY][c][q][y%TY][x] (TY = 2^tyl rows per tile, 1 by default):
+//  - row-interleaved, f[z][y/TY][c][q][y%TY][x] (TY = 2^tyl rows per tile, 8 by default;
+//    ceil(ny/TY) tiles per z plane, the last one padded with rows that are never
+//    addressed when TY does not divide ny: 254 rows cost 0.8% more memory and keep the
+//    8-row tiles, which a 2-row tiling (the largest power of two dividing 254) lost:
+//    33.8 against 39.5 GLUPS at 254^3):
 //    each x row of every population is a run of RP
 //    elements (nx rounded up to 256 bytes), and the C Q runs of one row lie together, so
 //    a workgroup's pulls touch a few contiguous blocks instead of 2 C Q separate streams.
@@ -172,7 +177,8 @@ StepParams base_params(const lbm_sim *s) {
 //    This is the default.
 // LBM_POP_LAYOUT=soa|rows selects one; LBM_POP_PAD overrides the SoA pad,
 // LBM_ROW_PAD adds to RP and LBM_BLOCK_PAD to the tile pitch (bytes, rounded down to
-// 256); LBM_ROW_TILE sets TY (a power of two dividing ny, else the next lower one).
+// 256); LBM_ROW_TILE sets TY (rounded down to a power of two).  TY shrinks only while
+// half of it still covers ny, so a short ny wastes less than half its tile.
 void pop_geometry(lbm_sim *s) {
     const uint64_t align = 256 / elem_size(s->storage);
     const uint64_t cq = uint64_t(s->C) * s->Q;
@@ -186,8 +192,8 @@ void pop_geometry(lbm_sim *s) {
         tyl = 0;
         while ((2 << tyl) <= ty && tyl < 6) tyl++;
     }
-    while (tyl > 0 && s->ny % (1 << tyl) != 0) tyl--;
-    const uint64_t tiles = uint64_t(s->ny >> tyl) * s->nz, ty = uint64_t(1) << tyl;
+    while (tyl > 0 && (1 << (tyl - 1)) >= s->ny) tyl--;
+    const uint64_t ty = uint64_t(1) << tyl, tiles = (uint64_t(s->ny) + ty - 1) / ty * s->nz;
     uint64_t block = cq * ty * RP, block_pad = 1024;
     if (const char *e = std::getenv("LBM_BLOCK_PAD")) block_pad = std::strtoull(e, nullptr, 10);
     block += block_pad / 256 * align;
@@ -294,6 +300,9 @@ int macro_into(lbm_sim *s, void *rho, void *u, int fp64, unsigned int *bad) {
 }
 
 bool valid_storage(int st) { return st >= LBM_F64 && st <= LBM_F16S; }
+
+// flag mode of the step kernels: 0 no flags, 1 walls, 2 walls and velocity nodes
+int flag_mode(const lbm_sim *s) { return s->has_walls ? (s->has_vel ? 2 : 1) : 0; }
 
 }  // namespace
 
@@ -426,6 +435,7 @@ int lbm_set_flags(lbm_sim *s, const uint8_t *flags) {
     HIPCHK(s, hipMemcpyAsync(s->flags_d, flags, s->N, hipMemcpyHostToDevice, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     s->has_walls = walls;
+    s->has_vel = vel;
     return LBM_OK;
 }
 
@@ -513,11 +523,11 @@ int lbm_step(lbm_sim *s, int n) {
         p.step = uint32_t(s->steps);
         hipError_t e;
         switch (s->model) {
-        case LBM_BGK: e = launch_step_bgk(s->lattice, s->storage, s->sr, lay, s->has_walls, p, cfg); break;
-        case LBM_MRT: e = launch_step_mrt(s->lattice, s->storage, s->sr, lay, s->has_walls, p, cfg); break;
-        case LBM_REGULARIZED: e = launch_step_reg(s->lattice, s->storage, s->sr, lay, s->has_walls, p, cfg); break;
-        case LBM_SMAGORINSKY: e = launch_step_smag(s->lattice, s->storage, s->sr, lay, s->has_walls, p, cfg); break;
-        case LBM_ELBM: e = launch_step_elbm(s->lattice, s->storage, lay, s->has_walls, p, cfg); break;
+        case LBM_BGK: e = launch_step_bgk(s->lattice, s->storage, s->sr, lay, flag_mode(s), p, cfg); break;
+        case LBM_MRT: e = launch_step_mrt(s->lattice, s->storage, s->sr, lay, flag_mode(s), p, cfg); break;
+        case LBM_REGULARIZED: e = launch_step_reg(s->lattice, s->storage, s->sr, lay, flag_mode(s), p, cfg); break;
+        case LBM_SMAGORINSKY: e = launch_step_smag(s->lattice, s->storage, s->sr, lay, flag_mode(s), p, cfg); break;
+        case LBM_ELBM: e = launch_step_elbm(s->lattice, s->storage, lay, flag_mode(s), p, cfg); break;
         default:
             e = launch_psi(s->lattice, s->storage, lay, p, cfg);
             if (e == hipSuccess) e = launch_step_sc(s->lattice, s->storage, lay, p, cfg);

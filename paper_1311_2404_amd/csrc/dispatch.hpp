@@ -52,17 +52,18 @@ hipError_t with_layout(int layout, F &&f) {
     }
 }
 
-// step kernels (step_bgk.hip, step_mrt.hip, step_elbm.hip, step_sc.hip)
-hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+// step kernels (step_bgk.hip, step_mrt.hip, step_elbm.hip, step_sc.hip); flags: 0 none,
+// 1 fluid and wall nodes, 2 also equilibrium velocity nodes
+hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                            const LaunchCfg &c);
-hipError_t launch_step_mrt(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+hipError_t launch_step_mrt(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                            const LaunchCfg &c);
 // step_reg.hip, step_smag.hip
-hipError_t launch_step_reg(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+hipError_t launch_step_reg(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                            const LaunchCfg &c);
-hipError_t launch_step_smag(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+hipError_t launch_step_smag(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                             const LaunchCfg &c);
-hipError_t launch_step_elbm(int lattice, int storage, int layout, bool flags, const StepParams &p,
+hipError_t launch_step_elbm(int lattice, int storage, int layout, int flags, const StepParams &p,
                             const LaunchCfg &c);
 hipError_t launch_step_sc(int lattice, int storage, int layout, const StepParams &p, const LaunchCfg &c);
 hipError_t launch_psi(int lattice, int storage, int layout, const StepParams &p, const LaunchCfg &c);

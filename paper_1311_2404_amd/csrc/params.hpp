@@ -20,7 +20,7 @@ struct StepParams {
     int nx, ny, nz;
     uint32_t N;                 // nodes per component
     uint32_t rp;                // population tile pitch: node (x, y, z) sits at offset
-    uint32_t rpitch;            // (z (ny >> tyl) + (y >> tyl)) rp + (y & (2^tyl - 1)) rpitch + x
+    uint32_t rpitch;            // (z ceil(ny / 2^tyl) + (y >> tyl)) rp + (y & (2^tyl - 1)) rpitch + x
     int tyl;                    // of a slot's block (SoA: rp = nx, tyl = 0)
     uint32_t S;                 // population stride in elements (>= N; padding spreads the
                                 // Q streams of a row over HBM channels)

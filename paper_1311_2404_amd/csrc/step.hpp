@@ -67,6 +67,7 @@ namespace lbm {
 struct Geo {
     int x, y, z, xm, xp, ym, yp, zm, zp;
     uint32_t nx, ny, rp, rpitch;
+    uint32_t nyt;  // tiles per z plane: ceil(ny / 2^tyl) (the last one padded when 2^tyl does not divide ny)
     int tyl;
     __device__ __forceinline__ uint32_t y_of(int dy) const { return uint32_t(dy == 0 ? y : (dy > 0 ? yp : ym)); }
     __device__ __forceinline__ uint32_t z_of(int dz) const { return uint32_t(dz == 0 ? z : (dz > 0 ? zp : zm)); }
@@ -77,7 +78,7 @@ struct Geo {
     // offset of the row of node (x, y + dy, z + dz) inside a population's block
     __device__ __forceinline__ uint32_t row_off(int dy, int dz) const {
         const uint32_t yy = y_of(dy);
-        return (z_of(dz) * (ny >> tyl) + (yy >> tyl)) * rp + (yy & ((1u << tyl) - 1u)) * rpitch;
+        return (z_of(dz) * nyt + (yy >> tyl)) * rp + (yy & ((1u << tyl) - 1u)) * rpitch;
     }
     __device__ __forceinline__ uint32_t pa(int dx, int dy, int dz) const { return row_off(dy, dz) + x_of(dx); }
 };
@@ -98,6 +99,7 @@ __device__ __forceinline__ Geo make_geo(int x, int y, int z, int nx, int ny, int
     g.ny = uint32_t(ny);
     g.rp = rp;
     g.rpitch = rpitch;
+    g.nyt = (uint32_t(ny) + (1u << tyl) - 1u) >> tyl;
     g.tyl = tyl;
     return g;
 }
@@ -194,7 +196,9 @@ __device__ __forceinline__ void velocity_node(const C *h, C *o, const StepParams
     }
 }
 
-template <class L, class St, int MODEL, int LAYOUT, bool FLAGS>
+// FLAGS: 0 no node flags, 1 fluid and wall nodes, 2 also equilibrium velocity nodes (the
+// velocity-node path is compiled only where such nodes exist).
+template <class L, class St, int MODEL, int LAYOUT, int FLAGS>
 __global__ __launch_bounds__(512) void k_step(StepParams p) {
     using T = typename St::T;
     using C = typename St::C;
@@ -224,9 +228,17 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         }
     }
 
+    // AB steps on padded rows (row-interleaved layout): lanes past the row's end run the
+    // step on the row's last node and store the result into the row's padding, which is
+    // never read.  Every store instruction of the row then writes whole memory sectors;
+    // a partly written 64-byte sector costs a read-modify-write (rows of 248-254 FP32
+    // nodes ran at 5.3-5.4 TB/s against 6.0 for 256).
     const bool active = x < p.nx && y < p.ny;
-    if (active) {
-        const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+    const bool pad = LAYOUT == LAYOUT_AB && x >= p.nx && x < int(p.rpitch) && y < p.ny;
+    if (active || pad) {
+        const Geo g = make_geo(active ? x : p.nx - 1, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+        Geo gs = g;  // where this lane stores (AB: its own x)
+        gs.x = x;
         const uint32_t n = g.at(0, 0, 0);
         const uint32_t S = p.S;
         // no __restrict__: with AA the two pointers are the same copy
@@ -242,7 +254,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         T out[Q];
         const uint32_t fl = FLAGS ? p.flags[n] : 0u;
         // equilibrium velocity nodes exist for the polynomial-equilibrium models
-        const bool vel = FLAGS && MODEL != M_ELBM && fl == 2u;
+        const bool vel = FLAGS == 2 && MODEL != M_ELBM && fl == 2u;
         if (fl == 1u) {
             // full-way bounce-back: the stored values are returned along -e_i untouched
 #pragma unroll
@@ -272,7 +284,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
 #pragma unroll
                 for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
                 conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
-                if (p.stats) {
+                if (p.stats && active) {
                     atomicAdd(&s_hist[ao.iters < NEWTON_BINS ? ao.iters : NEWTON_BINS - 1], 1u);
                     if (!ao.converged) atomicAdd(&s_hist[NEWTON_BINS], 1u);
                 }
@@ -295,7 +307,8 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         for (int i = 0; i < Q; i++) {
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), out[i]);
+            if constexpr (LAYOUT == LAYOUT_AB) LBM_STORE(pop_addr(dst, S, slot, gs, 0, 0, 0), out[i]);
+            else LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), out[i]);
         }
     }
     if constexpr (ELBM) {
@@ -512,7 +525,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
 // Launches k_step<MODEL> for every lattice, storage (with the stochastic-rounding
 // variants), layout and flag mode; one translation unit per model instantiates it.
 template <int MODEL>
-hipError_t launch_k_step(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+hipError_t launch_k_step(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                          const LaunchCfg &c) {
     return with_lattice(lattice, [&](auto lt) {
         using L = decltype(lt);
@@ -520,8 +533,9 @@ hipError_t launch_k_step(int lattice, int storage, int sr, int layout, bool flag
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
-                if (flags) k_step<L, St, MODEL, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
-                else k_step<L, St, MODEL, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                if (flags == 2) k_step<L, St, MODEL, LAY, 2><<<c.grid, c.block, 0, c.stream>>>(p);
+                else if (flags) k_step<L, St, MODEL, LAY, 1><<<c.grid, c.block, 0, c.stream>>>(p);
+                else k_step<L, St, MODEL, LAY, 0><<<c.grid, c.block, 0, c.stream>>>(p);
                 return hipGetLastError();
             });
         });

@@ -5,7 +5,7 @@
 
 namespace lbm {
 
-hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                            const LaunchCfg &c) {
     return with_lattice(lattice, [&](auto lt) {
         using L = decltype(lt);
@@ -14,7 +14,7 @@ hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, bool fl
 #if defined(LBM_VEC_STEP)
             // 16-byte accesses per population when the row fits a wave
             constexpr int VW = 16 / int(sizeof(typename St::T));
-            if (layout == LAYOUT_AB && vec_width(p.nx, int(sizeof(typename St::T))) == VW) {
+            if (layout == LAYOUT_AB && flags != 2 && vec_width(p.nx, int(sizeof(typename St::T))) == VW) {
                 const int R = p.nx / VW, by = 256 / R;
                 const dim3 grid(1, (p.ny + by - 1) / by, p.nz), block(R, by, 1);
                 if (flags) k_step_vec<L, St, M_BGK, true, VW><<<grid, block, 0, c.stream>>>(p);
@@ -24,8 +24,9 @@ hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, bool fl
 #endif
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
-                if (flags) k_step<L, St, M_BGK, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
-                else k_step<L, St, M_BGK, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                if (flags == 2) k_step<L, St, M_BGK, LAY, 2><<<c.grid, c.block, 0, c.stream>>>(p);
+                else if (flags) k_step<L, St, M_BGK, LAY, 1><<<c.grid, c.block, 0, c.stream>>>(p);
+                else k_step<L, St, M_BGK, LAY, 0><<<c.grid, c.block, 0, c.stream>>>(p);
                 return hipGetLastError();
             });
         });

@@ -4,7 +4,7 @@
 
 namespace lbm {
 
-hipError_t launch_step_elbm(int lattice, int storage, int layout, bool flags, const StepParams &p,
+hipError_t launch_step_elbm(int lattice, int storage, int layout, int flags, const StepParams &p,
                             const LaunchCfg &c) {
     return with_lattice(lattice, [&](auto lt) {
         using L = decltype(lt);
@@ -16,8 +16,8 @@ hipError_t launch_step_elbm(int lattice, int storage, int layout, bool flags, co
                     if (flags) k_step_elbm_mlp<L, St, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
                     else k_step_elbm_mlp<L, St, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
                 } else {
-                    if (flags) k_step<L, St, M_ELBM, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
-                    else k_step<L, St, M_ELBM, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                    if (flags) k_step<L, St, M_ELBM, LAY, 1><<<c.grid, c.block, 0, c.stream>>>(p);
+                    else k_step<L, St, M_ELBM, LAY, 0><<<c.grid, c.block, 0, c.stream>>>(p);
                 }
                 return hipGetLastError();
             });

@@ -4,7 +4,7 @@
 
 namespace lbm {
 
-hipError_t launch_step_smag(int lattice, int storage, int sr, int layout, bool flags, const StepParams &p,
+hipError_t launch_step_smag(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                             const LaunchCfg &c) {
     return launch_k_step<M_SMAG>(lattice, storage, sr, layout, flags, p, c);
 }

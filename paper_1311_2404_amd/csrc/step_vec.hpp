@@ -36,7 +36,8 @@ __global__ __launch_bounds__(256) void k_step_vec(StepParams p) {
         const int yy = dy == 0 ? y : (dy > 0 ? yp : ym);
         const int zz = dz == 0 ? z : (dz > 0 ? zp : zm);
         const uint32_t uy = uint32_t(yy);  // offset of the row in a population block
-        return (uint32_t(zz) * (uint32_t(p.ny) >> p.tyl) + (uy >> p.tyl)) * p.rp + (uy & ((1u << p.tyl) - 1u)) * p.rpitch;
+        const uint32_t nyt = (uint32_t(p.ny) + (1u << p.tyl) - 1u) >> p.tyl;
+        return (uint32_t(zz) * nyt + (uy >> p.tyl)) * p.rp + (uy & ((1u << p.tyl) - 1u)) * p.rpitch;
     };
     const T *src = static_cast<const T *>(p.src);
     T *dst = static_cast<T *>(p.dst);

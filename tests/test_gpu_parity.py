@@ -183,7 +183,8 @@ _LAYOUT_ENVS = [
     {"LBM_POP_LAYOUT": "rows", "LBM_BLOCK_PAD": "0"},
     {"LBM_POP_LAYOUT": "rows", "LBM_ROW_PAD": "768", "LBM_BLOCK_PAD": "2560"},
     {"LBM_POP_LAYOUT": "rows", "LBM_ROW_TILE": "2"},
-    {"LBM_POP_LAYOUT": "rows", "LBM_ROW_TILE": "8", "LBM_BLOCK_PAD": "0"},  # 8 does not divide ny: 4
+    {"LBM_POP_LAYOUT": "rows", "LBM_ROW_TILE": "8", "LBM_BLOCK_PAD": "0"},  # 8 does not divide ny: padded tile
+    {"LBM_POP_LAYOUT": "rows", "LBM_ROW_TILE": "32"},  # one tile larger than ny
 ]
 _LAYOUT_KEYS = ("LBM_POP_LAYOUT", "LBM_POP_PAD", "LBM_ROW_PAD", "LBM_BLOCK_PAD", "LBM_ROW_TILE")
 
