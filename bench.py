@@ -198,6 +198,46 @@ def run_extras(P, S, stream, torch):
     return out
 
 
+PRECISION_U0 = (0.0005, 0.001, 0.002, 0.005, 0.01, 0.02, 0.05, 0.1)
+
+
+def precision_sweep(P, S, stream, n=256, re=1000.0, u0s=PRECISION_U0, runs=None):
+    """The paper's single-precision study (Impact of single precision): D2Q9 LBGK decaying
+    Taylor-Green vortex on a periodic n^2 lattice at Re = u0 n / nu = 1000, every u0 run to
+    the same physical time (1e6 steps at u0 = 0.0005 on 256^2), here for every storage,
+    stochastic rounding included.  Velocity and density are compared with the analytic
+    solution, u = u0 (-cos kx sin ky, sin kx cos ky) exp(-2 nu k^2 t) and
+    rho - 1 = -(3/4) u0^2 (cos 2kx + cos 2ky) exp(-4 nu k^2 t), as relative L2 norms."""
+    import numpy as np
+    k = 2 * np.pi / n
+    x, y, _ = S._grid(n, n, 1)
+    runs = runs or [("f64", P.LBM_F64, 0), ("f32", P.LBM_F32, 0), ("f32s", P.LBM_F32S, 0),
+                    ("bf16s", P.LBM_BF16S, 0), ("bf16s_sr", P.LBM_BF16S, 1), ("f16s", P.LBM_F16S, 0),
+                    ("f16s_sr", P.LBM_F16S, 1)]
+    out = {}
+    for name, st, sr in runs:
+        rows = []
+        for u0 in u0s:
+            nu = u0 * n / re
+            steps = int(round(1e6 * 0.0005 / u0 * n / 256))
+            _, u = S.taylor_green_2d(n, n, u0)
+            drho = -0.75 * u0 ** 2 * (np.cos(2 * k * x) + np.cos(2 * k * y))
+            c = S.Case("tg2d", S.D2Q9, S.BGK, n, n, 1, S.tau_from_nu(nu), (0.0, 0.0, 0.0), steps, None,
+                       (1.0 + drho)[None], u)
+            s = P.Sim.from_case(c, st, P.LBM_AB, sr, stream=stream)
+            s.step(steps)
+            rho, ug = s.macro()
+            s.close()
+            ue = u * np.exp(-2 * nu * k * k * steps)
+            de = drho * np.exp(-4 * nu * k * k * steps)
+            rows.append({"u0": u0, "steps": steps,
+                         "vel_rel_l2": float(np.sqrt(((ug[:2] - ue) ** 2).sum() / (ue ** 2).sum())),
+                         "rho_rel_l2": float(np.sqrt(((rho[0] - 1.0 - de) ** 2).sum() / (de ** 2).sum()))})
+        out[name] = rows
+        print("[bench] precision sweep %s done" % name, file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +254,8 @@ def main():
                     help="skip the 1000-step velocity-error runs (for short profiled runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run 3 plain device copies of MIB MiB (calibrates HBM byte counters in profiles)")
+    ap.add_argument("--precision-sweep", action="store_true",
+                    help="run only the D2Q9 Taylor-Green precision study over u0 and storages (JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -229,6 +271,12 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
+    if args.precision_sweep:
+        t0 = time.perf_counter()
+        res = precision_sweep(P, S, stream)
+        print(json.dumps({"precision_sweep": res, "lattice": "D2Q9 256^2", "re": 1000,
+                          "wall_s": round(time.perf_counter() - t0, 1)}))
+        return
     layout = P.LBM_AA if args.layout == "aa" else P.LBM_AB
     n = args.n
     N = n ** 3
