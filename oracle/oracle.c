@@ -39,6 +39,9 @@
  *    node; rho is summed after that; the node's post-collision state is the polynomial
  *    feq(rho, u_bc), with no relaxation and no force.  The macroscopic output of such
  *    a node is that rho and u_bc.  Single-component polynomial-equilibrium models only.
+ *  - Half-way bounce-back nodes (flag 3): wet nodes; the missing populations (as above)
+ *    are the reflections of those that reached the node in this step, and the node then
+ *    collides like any fluid node.  Its macroscopic output is that of the completed set.
  */
 #include "oracle.h"
 
@@ -713,17 +716,24 @@ static void sc_force(const orc_params *P, const lattice_t *L, const double *psi,
     for (int a = 0; a < 3; a++) F[a] = -P->G * psi[c * N + n] * s[a] + rho_c * P->g[a];
 }
 
-/* Equilibrium velocity node (boundary conditions subsection): the populations that
- * stream in from wall nodes are missing and are replaced by the opposite population of
- * the same node (bounce-back); returns drho = sum of the completed set (as h). */
-static double velocity_node_drho(const orc_params *P, const lattice_t *L, const uint8_t *flags, int64_t x,
-                                 int64_t y, int64_t z, const double *h) {
-    double drho = 0.0;
+/* Boundary nodes (boundary conditions subsection): the populations that stream in
+ * from wall nodes are missing and take the value of the opposite population of the same
+ * node (bounce-back).  hc = the completed set (as h). */
+static void complete_missing(const orc_params *P, const lattice_t *L, const uint8_t *flags, int64_t x, int64_t y,
+                             int64_t z, const double *h, double *hc) {
     for (int i = 0; i < L->q; i++) {
         int back[3] = {-L->e[i][0], -L->e[i][1], -L->e[i][2]};
         int missing = flags[neighbour(P, x, y, z, back)] == 1;
-        drho += missing ? h[L->opp[i]] : h[i];
+        hc[i] = missing ? h[L->opp[i]] : h[i];
     }
+}
+
+/* Equilibrium velocity node: returns drho = sum of the completed set. */
+static double velocity_node_drho(const orc_params *P, const lattice_t *L, const uint8_t *flags, int64_t x,
+                                 int64_t y, int64_t z, const double *h) {
+    double hc[QMAX], drho = 0.0;
+    complete_missing(P, L, flags, x, y, z, h, hc);
+    for (int i = 0; i < L->q; i++) drho += hc[i];
     return drho;
 }
 
@@ -764,7 +774,7 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
             if (flags[n]) return -2; /* walls are not defined for the two-component model */
     if (flags)
         for (int64_t n = 0; n < N; n++)
-            if (flags[n] > 2 || (flags[n] == 2 && P->model == ORC_ELBM)) return -2;
+            if (flags[n] > 3 || (flags[n] >= 2 && P->model == ORC_ELBM)) return -2;
     double *cur = (double *)malloc(sizeof(double) * C * q * N);
     double *nxt = (double *)malloc(sizeof(double) * C * q * N);
     double *psi = C == 2 ? (double *)malloc(sizeof(double) * 2 * N) : NULL;
@@ -803,6 +813,12 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
             } else if (flags && flags[n] == 2) {
                 double drho = velocity_node_drho(P, &L, flags, x, y, z, hl[0]);
                 heq_poly(&L, drho, P->u_bc, post[0]);
+            } else if (flags && flags[n] == 3) {
+                /* half-way bounce-back node: wet; the missing populations are the reflections
+                 * of the ones that reached the node in this step, then the node collides */
+                double hc[QMAX];
+                complete_missing(P, &L, flags, x, y, z, hl[0], hc);
+                collide_single(P, &L, hc, post[0], NULL);
             } else if (C == 1) {
                 node_info info = {0, 1};
                 collide_single(P, &L, hl[0], post[0], &info);
@@ -880,6 +896,11 @@ int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double
         double rc[2], jc[2][3], hl[QMAX], dr;
         for (int c = 0; c < C; c++) {
             for (int i = 0; i < q; i++) hl[i] = f[((int64_t)c * q + i) * N + n] - L.w[i];
+            if (flags && flags[n] == 3 && C == 1) {
+                double hc[QMAX];
+                complete_missing(P, &L, flags, x, y, z, hl, hc);
+                memcpy(hl, hc, sizeof(double) * q);
+            }
             moments(&L, hl, &dr, jc[c]);
             rc[c] = 1.0 + dr;
             rho[c * N + n] = rc[c];

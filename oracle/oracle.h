@@ -15,7 +15,7 @@
  *
  * Array layouts: populations f[C][Q][N], N = nx*ny*nz with x fastest
  * (node n = x + nx*(y + ny*z)); flags[N] (0 fluid, 1 full-way bounce-back wall,
- * 2 equilibrium velocity node with the velocity u_bc);
+ * 2 equilibrium velocity node with the velocity u_bc, 3 half-way bounce-back node);
  * densities rho[C][N]; velocities u[3][N] (the z row is zero on D2Q9).
  *
  * Parity unpinned (no printed values in the paper): the MRT, ELBM,

@@ -64,7 +64,7 @@ def uniform_pm(seed: int, stream: int, shape, amp: float, dtype=np.float64) -> n
 # lattice identifiers shared with the C ABI (plain integers, no tables)
 D2Q9, D3Q19 = 0, 1
 BGK, MRT, ELBM, SHANCHEN, REG, SMAG = 0, 1, 2, 3, 4, 5
-FLUID, WALL, VELOCITY = 0, 1, 2
+FLUID, WALL, VELOCITY, HALFWAY = 0, 1, 2, 3
 Q_OF = {D2Q9: 9, D3Q19: 19}
 D_OF = {D2Q9: 2, D3Q19: 3}
 
@@ -188,6 +188,17 @@ def couette_flags(nx, ny, nz):
     fl = np.zeros((nz, ny, nx), dtype=np.uint8)
     fl[:, :, 0] = VELOCITY
     fl[:, :, nx - 1] = WALL
+    return fl
+
+
+def halfway_channel_flags_2d(nx, ny):
+    """Channel for half-way bounce-back: dry walls on y = 0 and y = ny-1, half-way
+    bounce-back (wet) nodes on y = 1 and y = ny-2, fluid between; periodic in x."""
+    fl = np.zeros((1, ny, nx), dtype=np.uint8)
+    fl[:, 0, :] = WALL
+    fl[:, ny - 1, :] = WALL
+    fl[:, 1, :] = HALFWAY
+    fl[:, ny - 2, :] = HALFWAY
     return fl
 
 

@@ -943,3 +943,66 @@ def test_velocity_node_rule_on_random_state():
                     assert abs(dst - fe[i]) <= 4e-16, (x, y, z, i)
                 checked += 1
     assert checked == (n - 2) ** 2
+
+
+# --------------------------------------------------------------------------- half-way bounce-back nodes
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0, 1.4])
+def test_halfway_channel_steady_parabola(tau):
+    """Force-driven channel between half-way bounce-back nodes (y = 1, ny - 2) backed by dry
+    walls: the steady profile is a parabola with the Navier-Stokes curvature -g/nu, its two
+    zeros are symmetric, and they lie beyond the wet wall nodes, as the boundary-condition
+    subsection places the wall."""
+    nx, ny, g = 4, 14, 1e-6
+    rho, u = S.rest_fields(nx, ny, 1, 2)
+    o = oracle.Oracle(S.D2Q9, S.BGK, nx, ny, 1, tau, (g, 0.0, 0.0))
+    o.set_flags(S.halfway_channel_flags_2d(nx, ny))
+    o.init_eq(rho, u)
+    prev = None
+    for _ in range(400):
+        o.run(2000)
+        _, v = o.macro()
+        ux = v[0].reshape(ny, nx)[:, 0].copy()
+        if prev is not None and np.abs(ux - prev).max() < 1e-20:
+            break
+        prev = ux
+    ys = np.arange(1, ny - 1)
+    c = np.polyfit(ys, ux[1:ny - 1], 2)
+    assert np.abs(np.polyval(c, ys) - ux[1:ny - 1]).max() < 1e-15
+    nu = (tau - 0.5) / 3
+    assert abs(2 * c[0] / (-g / nu) - 1) < 1e-9
+    lo, hi = sorted(np.roots(c).real)
+    assert abs(lo + hi - (ny - 1)) < 1e-9
+    assert 0.5 < lo < 1.0
+    assert np.abs(v[1]).max() < 1e-15
+
+
+def test_halfway_node_rule_on_random_state():
+    """One step from a random state, applied by hand at every half-way node: the
+    populations streamed from dry wall nodes take the value of the node's opposite
+    population, the completed set collides like a fluid node (the collision pinned above),
+    and the result streams to x + e_i."""
+    nx, ny, tau, g = 8, 10, 0.7, (2e-5, -1e-5, 0.0)
+    o = oracle.Oracle(S.D2Q9, S.BGK, nx, ny, 1, tau, g)
+    flags = S.halfway_channel_flags_2d(nx, ny)
+    o.set_flags(flags)
+    e, w, opp = oracle.tables(S.D2Q9)
+    rng = np.random.default_rng(41)
+    f0 = w[:, None] * (1 + 0.2 * (2 * rng.random((9, nx * ny)) - 1))
+    o.set_f(f0[None])
+    rho_out, u_out = o.macro()
+    o.run(1)
+    F0, F1, fl = f0.reshape(9, ny, nx), o.f[0].reshape(9, ny, nx), flags.reshape(ny, nx)
+    checked = 0
+    for y in range(ny):
+        for x in range(nx):
+            if fl[y, x] != S.HALFWAY:
+                continue
+            comp = np.array([F0[opp[i], y, x] if fl[(y - e[i, 1]) % ny, (x - e[i, 0]) % nx] == S.WALL else F0[i, y, x]
+                             for i in range(9)])
+            assert abs(rho_out[0].reshape(ny, nx)[y, x] - comp.sum()) <= 2e-15
+            post = o.collide_node(comp)
+            for i in range(9):
+                assert abs(F1[i, (y + e[i, 1]) % ny, (x + e[i, 0]) % nx] - post[i]) <= 4e-16, (x, y, i)
+            checked += 1
+    assert checked == 2 * nx
