@@ -57,12 +57,15 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_BF16S = 3, LBM_F16S = 4 };
 /* Streaming pattern (GPU-algorithms subsection): AB = two copies, ping-pong;
  * AA = one copy updated in place, even and odd steps access different slots. */
 enum { LBM_AB = 0, LBM_AA = 1 };
-/* uint8 node flags: fluid; full-way bounce-back wall (a dry node that returns what it
- * receives, boundary-conditions subsection); equilibrium velocity node (a fluid node on
- * a domain face whose populations streamed in from wall nodes are missing: each takes
- * the value of its opposite at the node, rho is summed over the completed set, and the
- * node leaves feq(rho, u_bc), the equilibrium approach of the same subsection). */
-enum { LBM_FLUID = 0, LBM_WALL_BB = 1, LBM_VELOCITY = 2 };
+/* uint8 node flags (boundary-conditions subsection): fluid; full-way bounce-back wall (a
+ * dry node that returns what it receives); equilibrium velocity node (a fluid node on a
+ * domain face whose populations streamed in from wall nodes are missing: each takes the
+ * value of its opposite at the node, rho is summed over the completed set, and the node
+ * leaves feq(rho, u_bc), the equilibrium approach); half-way bounce-back node (a wet
+ * node next to wall nodes: its missing populations are completed the same way, which
+ * reflects what reached it in the same step, and it then collides as a fluid node; the
+ * wall lies beyond it). */
+enum { LBM_FLUID = 0, LBM_WALL_BB = 1, LBM_VELOCITY = 2, LBM_HALFWAY_BB = 3 };
 enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,      /* invalid argument */
@@ -120,9 +123,11 @@ int lbm_set_smagorinsky(lbm_sim *sim, double cs);
  * NULL = the null stream. */
 int lbm_set_stream(lbm_sim *sim, void *hip_stream);
 
-/* Node flags, host array uint8[N] (LBM_FLUID / LBM_WALL_BB / LBM_VELOCITY), copied.
- * Before or after init.  Values above 2: LBM_EINVAL.  Walls are not supported with
- * LBM_SHANCHEN, velocity nodes not with LBM_SHANCHEN or LBM_ELBM (LBM_EUNSUPPORTED). */
+/* Node flags, host array uint8[N] (LBM_FLUID / LBM_WALL_BB / LBM_VELOCITY /
+ * LBM_HALFWAY_BB), copied.  Before or after init.  Values above 3: LBM_EINVAL.  Walls
+ * are not supported with LBM_SHANCHEN, velocity and half-way nodes not with LBM_SHANCHEN
+ * or LBM_ELBM (LBM_EUNSUPPORTED).  The macroscopic output of a half-way node is that of
+ * its completed population set. */
 int lbm_set_flags(lbm_sim *sim, const uint8_t *flags);
 
 /* Initialise f = f_eq(rho, u) (the entropic equilibrium for ELBM, else the polynomial

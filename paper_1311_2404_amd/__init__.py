@@ -21,7 +21,7 @@ LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_BGK, LBM_MRT, LBM_ELBM, LBM_SHANCHEN, LBM_REGULARIZED, LBM_SMAGORINSKY = 0, 1, 2, 3, 4, 5
 LBM_F64, LBM_F32, LBM_F32S, LBM_BF16S, LBM_F16S = 0, 1, 2, 3, 4
 LBM_AB, LBM_AA = 0, 1
-LBM_FLUID, LBM_WALL_BB, LBM_VELOCITY = 0, 1, 2
+LBM_FLUID, LBM_WALL_BB, LBM_VELOCITY, LBM_HALFWAY_BB = 0, 1, 2, 3
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSUPPORTED, LBM_EDIVERGED = 0, -1, -2, -3, -4, -5, -6
 MLP_NPARAM = 1313
 MLP_NTOTAL = 1325  # weights + input normalisation mu[6], isd[6]

@@ -40,7 +40,7 @@ struct lbm_sim {
     int cur = 0;
     uint8_t *flags_d = nullptr;
     bool has_walls = false;
-    bool has_vel = false;  // some node is an equilibrium velocity node
+    bool has_vel = false;  // some node is a boundary node (velocity or half-way bounce-back)
     void *psi_d = nullptr;
     double *stage = nullptr;
     double *macro_d = nullptr;  // FP64 rho[C][N] + u[3][N] scratch for lbm_macro / lbm_diag
@@ -301,7 +301,7 @@ int macro_into(lbm_sim *s, void *rho, void *u, int fp64, unsigned int *bad) {
 
 bool valid_storage(int st) { return st >= LBM_F64 && st <= LBM_F16S; }
 
-// flag mode of the step kernels: 0 no flags, 1 walls, 2 walls and velocity nodes
+// flag mode of the step kernels: 0 no flags, 1 walls, 2 walls and boundary nodes
 int flag_mode(const lbm_sim *s) { return s->has_walls ? (s->has_vel ? 2 : 1) : 0; }
 
 }  // namespace
@@ -422,14 +422,14 @@ int lbm_set_flags(lbm_sim *s, const uint8_t *flags) {
     if (!flags) return fail(s, LBM_EINVAL, "flags is NULL");
     bool walls = false, vel = false;
     for (uint32_t n = 0; n < s->N; n++) {
-        if (flags[n] > LBM_VELOCITY) return fail(s, LBM_EINVAL, "flag values must be 0, 1 or 2");
+        if (flags[n] > LBM_HALFWAY_BB) return fail(s, LBM_EINVAL, "flag values must be 0 to 3");
         walls = walls || flags[n] != LBM_FLUID;
-        vel = vel || flags[n] == LBM_VELOCITY;
+        vel = vel || flags[n] >= LBM_VELOCITY;
     }
     if (walls && s->model == LBM_SHANCHEN)
         return fail(s, LBM_EUNSUPPORTED, "walls are not supported with the Shan-Chen model");
     if (vel && s->model == LBM_ELBM)
-        return fail(s, LBM_EUNSUPPORTED, "velocity nodes are built for the polynomial-equilibrium models");
+        return fail(s, LBM_EUNSUPPORTED, "boundary nodes are built for the polynomial-equilibrium models");
     HIPCHK(s, hipSetDevice(s->device));
     if (!s->flags_d) HIPCHK(s, hipMalloc(&s->flags_d, s->N));
     HIPCHK(s, hipMemcpyAsync(s->flags_d, flags, s->N, hipMemcpyHostToDevice, s->stream));

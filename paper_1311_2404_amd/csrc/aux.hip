@@ -112,7 +112,8 @@ __global__ void k_set_plane(PlaneParams p) {
 // Macroscopic output.  Density per component; velocity (j + F/2)/rho for the forced
 // single-component models, j/rho for ELBM, the mixture velocity for Shan-Chen; 0 on walls.
 // Equilibrium velocity nodes report the density of their completed population set (the
-// populations streamed from walls replaced by their opposites) and the prescribed velocity.
+// populations streamed from walls replaced by their opposites) and the prescribed velocity;
+// half-way bounce-back nodes report the moments of their completed set.
 template <class L, class St>
 __global__ void k_macro(MacroParams p) {
     using T = typename St::T;
@@ -123,6 +124,7 @@ __global__ void k_macro(MacroParams p) {
     double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
     const uint32_t fl = p.flags ? p.flags[n] : 0u;
     const bool vel = fl == 2u && p.ncomp == 1;
+    const bool half = fl == 3u && p.ncomp == 1;
     for (int c = 0; c < p.ncomp; c++) {
         const T *pop = static_cast<const T *>(p.pop) + size_t(c) * L::Q * p.S;
         C h[L::Q];
@@ -132,6 +134,15 @@ __global__ void k_macro(MacroParams p) {
             uint32_t nd;
             canon_loc<L>(p.layout, i, g, slot, nd);
             h[i] = St::decode(pop[size_t(slot) * p.S + nd], C(L::w(i)));
+        }
+        if (half) {
+            // half-way bounce-back node: the moments of the completed set
+            C hb[L::Q];
+#pragma unroll
+            for (int i = 0; i < L::Q; i++) hb[i] = h[i];
+#pragma unroll
+            for (int i = 0; i < L::Q; i++)
+                if (p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1) h[i] = hb[opp(i)];
         }
         const Macro<C> m = moments<L, C>(h);
         rho[c] = double(m.rho);

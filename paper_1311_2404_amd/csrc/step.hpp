@@ -174,6 +174,20 @@ __device__ __forceinline__ void post_loc(int layout, int i, const Geo &g, int &s
     }
 }
 
+// Half-way bounce-back node (boundary-conditions subsection): a wet node whose
+// populations streamed in from wall nodes are missing; each takes the value of the
+// node's opposite population, i.e. what reached the node moving towards the wall is
+// reflected in the same step.  The node then collides as a fluid node.
+template <class L, class C>
+__device__ __forceinline__ void complete_missing(C *h, const StepParams &p, const Geo &g) {
+    C hb[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) hb[i] = h[i];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+        if (p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1) h[i] = hb[opp(i)];
+}
+
 // Equilibrium velocity node (boundary-conditions subsection): a population that streams
 // in from a wall node is missing and takes the value of the node's opposite population;
 // rho sums the completed set; the node leaves feq(rho, u_bc) (no relaxation, no force).
@@ -196,8 +210,8 @@ __device__ __forceinline__ void velocity_node(const C *h, C *o, const StepParams
     }
 }
 
-// FLAGS: 0 no node flags, 1 fluid and wall nodes, 2 also equilibrium velocity nodes (the
-// velocity-node path is compiled only where such nodes exist).
+// FLAGS: 0 no node flags, 1 fluid and wall nodes, 2 also boundary nodes (equilibrium
+// velocity and half-way bounce-back; their paths are compiled only where they exist).
 template <class L, class St, int MODEL, int LAYOUT, int FLAGS>
 __global__ __launch_bounds__(512) void k_step(StepParams p) {
     using T = typename St::T;
@@ -263,6 +277,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             C h[Q], o[Q];
 #pragma unroll
             for (int i = 0; i < Q; i++) h[i] = St::decode(raw[i], C(L::w(i)));
+            if (FLAGS == 2 && MODEL != M_ELBM && fl == 3u) complete_missing<L, C>(h, p, g);
             if (vel) {
                 velocity_node<L, C>(h, o, p, g);
             } else if constexpr (MODEL == M_BGK) {

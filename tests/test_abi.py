@@ -96,7 +96,7 @@ def test_shan_chen_rejects_walls_and_sr(lbm):
         with pytest.raises(lbm.LbmError) as ei:
             lbm.lbm_set_storage(h, lbm.LBM_BF16S, lbm.LBM_AB, 1)
         assert ei.value.code == lbm.LBM_EUNSUPPORTED
-        bad = np.full(64, 3, np.uint8)
+        bad = np.full(64, 4, np.uint8)
         with pytest.raises(lbm.LbmError) as ei:
             lbm.lbm_set_flags(h, bad)
         assert ei.value.code == lbm.LBM_EINVAL
@@ -128,16 +128,17 @@ def test_regularized_and_smagorinsky_arguments(lbm):
 
 
 def test_velocity_nodes_arguments(lbm):
-    fl = np.zeros(64, np.uint8)
-    fl[:16] = lbm.LBM_VELOCITY
-    for model in (lbm.LBM_ELBM, lbm.LBM_SHANCHEN):
-        h = lbm.lbm_create(lbm.LBM_D3Q19, model, 4, 4, 4, 0.6)
-        try:
-            with pytest.raises(lbm.LbmError) as ei:
-                lbm.lbm_set_flags(h, fl)
-            assert ei.value.code == lbm.LBM_EUNSUPPORTED
-        finally:
-            lbm.lbm_destroy(h)
+    for kind in (lbm.LBM_VELOCITY, lbm.LBM_HALFWAY_BB):
+        fl = np.zeros(64, np.uint8)
+        fl[:16] = kind
+        for model in (lbm.LBM_ELBM, lbm.LBM_SHANCHEN):
+            h = lbm.lbm_create(lbm.LBM_D3Q19, model, 4, 4, 4, 0.6)
+            try:
+                with pytest.raises(lbm.LbmError) as ei:
+                    lbm.lbm_set_flags(h, fl)
+                assert ei.value.code == lbm.LBM_EUNSUPPORTED
+            finally:
+                lbm.lbm_destroy(h)
     h = lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_BGK, 4, 4, 4, 0.6)
     try:
         lbm.lbm_set_velocity_bc(h, (0.0, 0.05, 0.0))

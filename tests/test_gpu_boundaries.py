@@ -77,3 +77,36 @@ def test_cavity_population_layouts_agree_bitwise(monkeypatch):
                     assert np.array_equal(a, b), (st, lay, env)
             for k in _LAYOUT_KEYS:
                 monkeypatch.delenv(k, raising=False)
+
+
+def halfway_channel(lattice, model, nx, ny, nz, tau=0.6, force=(2e-5, 0.0, 0.0), seed=3):
+    """Channel along x with dry walls on y = 0, ny - 1 and half-way bounce-back nodes on
+    y = 1, ny - 2, from a seeded random state."""
+    d = 2 if lattice == S.D2Q9 else 3
+    rho, u = S.random_state_fields(nx, ny, nz, d, seed, 0.03, 0.01)
+    fl = np.zeros((nz, ny, nx), np.uint8)
+    fl[:, 0, :] = S.WALL
+    fl[:, ny - 1, :] = S.WALL
+    fl[:, 1, :] = S.HALFWAY
+    fl[:, ny - 2, :] = S.HALFWAY
+    rates = None
+    if model == S.MRT:
+        rates = (S.mrt_rates_d2q9 if lattice == S.D2Q9 else S.mrt_rates_d3q19)(1 / tau, 1.2)
+    if model == S.REG:
+        force = (0.0, 0.0, 0.0)
+    return S.Case("halfway", lattice, model, nx, ny, nz, tau, force, 0, fl, rho, u, mrt_rates=rates, cs_smag=0.2)
+
+
+@pytest.mark.parametrize("model", [S.BGK, S.MRT, S.REG, S.SMAG])
+@pytest.mark.parametrize("lattice,shape", [(S.D2Q9, (130, 19, 1)), (S.D3Q19, (70, 13, 6))])
+def test_halfway_channel_fp64(model, lattice, shape):
+    check_f64(halfway_channel(lattice, model, *shape), 60)
+
+
+@pytest.mark.parametrize("storage", [P.LBM_F64, P.LBM_F32, P.LBM_BF16S])
+def test_halfway_aa_equals_ab_bitwise(storage):
+    c = halfway_channel(S.D3Q19, S.BGK, 40, 11, 9)
+    for steps in (1, 6, 7):
+        fa, ra, ua = gpu_run(c, steps, storage, P.LBM_AB)
+        fb, rb, ub = gpu_run(c, steps, storage, P.LBM_AA)
+        assert np.array_equal(fa, fb) and np.array_equal(ua, ub) and np.array_equal(ra, rb), (storage, steps)
