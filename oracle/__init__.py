@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC = os.path.join(_HERE, "oracle.c")
 
 D2Q9, D3Q19 = 0, 1
-BGK, MRT, ELBM, SHANCHEN, REG, SMAG = 0, 1, 2, 3, 4, 5
+BGK, MRT, ELBM, SHANCHEN, REG, SMAG, FREE_ENERGY = 0, 1, 2, 3, 4, 5, 6
 MLP_NPARAM = 1313
 MLP_NTOTAL = 1325  # weights + input normalisation mu[6], isd[6]
 
@@ -39,7 +39,9 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("g", C.c_double * 3), ("s", C.c_double * 19),
                 ("alpha_init", C.c_int), ("alpha_tol", C.c_double), ("alpha_maxit", C.c_int),
                 ("mlp", C.POINTER(C.c_double)), ("G", C.c_double), ("psi", C.c_int),
-                ("cs_smag", C.c_double), ("u_bc", C.c_double * 3)]
+                ("cs_smag", C.c_double), ("u_bc", C.c_double * 3),
+                ("tau_b", C.c_double), ("tau_phi", C.c_double), ("fe_a", C.c_double), ("fe_kappa", C.c_double),
+                ("fe_gamma", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -77,6 +79,10 @@ def lib():
         L.orc_init_eq.argtypes = [P, dp, dp, dp, dp]
         L.orc_run.argtypes = [P, C.c_void_p, dp, C.c_int, C.POINTER(Stats)]
         L.orc_macro.argtypes = [P, C.c_void_p, dp, dp, dp]
+        L.orc_fe_equilibria.argtypes = [P, C.c_double, C.c_double, dp, dp, C.c_double, dp, dp]
+        L.orc_fe_equilibria.restype = None
+        L.orc_fe_stencil.argtypes = [P, C.c_void_p, dp, C.c_int, C.c_int, C.c_int, dp, dp]
+        L.orc_fe_stencil.restype = None
         _lib = L
     return _lib
 
@@ -175,7 +181,7 @@ class Oracle:
 
     def __init__(self, lattice, model, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), mrt_rates=None,
                  alpha_init=0, alpha_tol=1e-10, alpha_maxit=20, mlp=None, G=0.0, psi=0, cs_smag=0.1,
-                 u_bc=(0.0, 0.0, 0.0)):
+                 u_bc=(0.0, 0.0, 0.0), fe=None):
         self.p = Params()
         self.p.lattice, self.p.model = lattice, model
         self.p.nx, self.p.ny, self.p.nz = nx, ny, nz
@@ -192,9 +198,12 @@ class Oracle:
         self.p.cs_smag = cs_smag
         for a in range(3):
             self.p.u_bc[a] = float(u_bc[a]) if a < len(u_bc) else 0.0
+        if fe is not None:
+            self.p.tau_b, self.p.tau_phi = fe["tau_b"], fe["tau_phi"]
+            self.p.fe_a, self.p.fe_kappa, self.p.fe_gamma = fe["a"], fe["kappa"], fe["gamma"]
         self.q = q_of(lattice)
         self.n = nx * ny * nz
-        self.ncomp = 2 if model == SHANCHEN else 1
+        self.ncomp = 2 if model in (SHANCHEN, FREE_ENERGY) else 1
         self.f = np.zeros((self.ncomp, self.q, self.n))
         self.flags = None
         self.stats = Stats()
@@ -203,6 +212,7 @@ class Oracle:
     def from_case(cls, case, **kw):
         kw.setdefault("cs_smag", case.cs_smag)
         kw.setdefault("u_bc", case.u_bc)
+        kw.setdefault("fe", case.fe)
         o = cls(case.lattice, case.model, case.nx, case.ny, case.nz, case.tau, case.force,
                 case.mrt_rates, G=case.G, psi=case.psi, **kw)
         if case.flags is not None:
@@ -253,6 +263,20 @@ class Oracle:
         if rc:
             raise ValueError("oracle macro rejected the parameters (%d)" % rc)
         return rho, u
+
+    def fe_equilibria(self, rho, phi, u, grad, lap):
+        fe, ge = np.zeros(self.q), np.zeros(self.q)
+        lib().orc_fe_equilibria(C.byref(self.p), rho, phi, _dp(_f64(list(u) + [0.0] * (3 - len(u)))),
+                                _dp(_f64(list(grad) + [0.0] * (3 - len(grad)))), lap, _dp(fe), _dp(ge))
+        return fe, ge
+
+    def fe_stencil(self, phi, x, y, z, flags=None):
+        grad, lap = np.zeros(3), C.c_double()
+        fl = np.ascontiguousarray(flags, dtype=np.uint8).reshape(-1) if flags is not None else None
+        ph = _f64(phi).reshape(-1)
+        lib().orc_fe_stencil(C.byref(self.p), fl.ctypes.data if fl is not None else None, _dp(ph), x, y, z,
+                             _dp(grad), C.byref(lap))
+        return grad, lap.value
 
     def newton_hist(self):
         return np.array(self.stats.newton_hist[:]), self.stats.nonconverged, self.stats.nodes

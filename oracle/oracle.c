@@ -42,6 +42,16 @@
  *  - Half-way bounce-back nodes (flag 3): wet nodes; the missing populations (as above)
  *    are the reflections of those that reached the node in this step, and the node then
  *    collides like any fluid node.  Its macroscopic output is that of the completed set.
+ *  - Free-energy model: the weights the paper takes from the literature are fixed here by
+ *    the moment conditions they must meet: with lattice weights t_i, the non-rest weights
+ *    are 3 t_i and the gradient weights t_i (4.5 e_a e_b - 3 d_ab), so that sum_i feq_i e e
+ *    is P_ab + rho u u; the rest populations take what mass (rho, phi) leaves.  The bulk
+ *    pressure is rho/3 + A (-phi^2/2 + 3 phi^4/4) (the sign of phi^2 that matches
+ *    mu = A(-phi + phi^3)).  Gradient and Laplacian use the isotropic lattice-weight
+ *    stencils; a wall neighbour contributes phi(x) (neutral wetting).  The body force
+ *    enters f by the exact difference method around u = j/rho; g's equilibrium takes
+ *    the velocity (j + F/2)/rho.  Initial populations are the equilibria with zero phi
+ *    gradients.
  */
 #include "oracle.h"
 
@@ -681,7 +691,8 @@ void orc_collide_node_sc(const orc_params *P, const double *f2, const double *ps
 
 static int check_params(const orc_params *P) {
     if (P->lattice != ORC_D2Q9 && P->lattice != ORC_D3Q19) return -1;
-    if (P->model < ORC_BGK || P->model > ORC_SMAG) return -1;
+    if (P->model < ORC_BGK || P->model > ORC_FREE_ENERGY) return -1;
+    if (P->model == ORC_FREE_ENERGY && !(P->tau_b > 0.5 && P->tau_phi > 0.5)) return -1;
     if (P->nx <= 0 || P->ny <= 0 || P->nz <= 0) return -1;
     if (P->lattice == ORC_D2Q9 && P->nz != 1) return -1;
     if (!(P->tau > 0.5)) return -1;
@@ -737,16 +748,119 @@ static double velocity_node_drho(const orc_params *P, const lattice_t *L, const 
     return drho;
 }
 
+/* ---- free-energy binary model (free energy model subsection) ---------------------- */
+
+static int ncomp_of(const orc_params *P) {
+    return P->model == ORC_SHANCHEN || P->model == ORC_FREE_ENERGY ? 2 : 1;
+}
+
+/* d_a phi = 3 sum_i t_i e_ia phi(x + e_i), lap phi = 6 sum_i t_i (phi(x + e_i) - phi(x)) */
+static void fe_stencil(const orc_params *P, const lattice_t *L, const uint8_t *flags, const double *phi,
+                       int64_t x, int64_t y, int64_t z, double *grad, double *lap) {
+    const int64_t n = x + P->nx * (y + P->ny * z);
+    const double p0 = phi[n];
+    double l = 0.0;
+    grad[0] = grad[1] = grad[2] = 0.0;
+    for (int i = 1; i < L->q; i++) {
+        const int64_t m = neighbour(P, x, y, z, L->e[i]);
+        const double pn = (flags && flags[m] == 1) ? p0 : phi[m];
+        for (int a = 0; a < 3; a++) grad[a] += 3.0 * L->w[i] * L->e[i][a] * pn;
+        l += 6.0 * L->w[i] * (pn - p0);
+    }
+    *lap = l;
+}
+
+void orc_fe_stencil(const orc_params *P, const uint8_t *flags, const double *phi, int x, int y, int z,
+                    double *grad, double *lap) {
+    lattice_t L;
+    make_lattice(P->lattice, &L);
+    fe_stencil(P, &L, flags, phi, x, y, z, grad, lap);
+}
+
+static void fe_equilibria(const orc_params *P, const lattice_t *L, double rho, double phi, const double *u,
+                          const double *grad, double lap, double *feq, double *geq) {
+    const double A = P->fe_a, k = P->fe_kappa;
+    const double mu = A * (-phi + phi * phi * phi) - k * lap;
+    const double p0 = rho / 3.0 + A * (-0.5 * phi * phi + 0.75 * phi * phi * phi * phi);
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double g2 = grad[0] * grad[0] + grad[1] * grad[1] + grad[2] * grad[2];
+    double fs = 0.0, gs = 0.0;
+    for (int i = 1; i < L->q; i++) {
+        const double t = L->w[i];
+        const double eu = L->e[i][0] * u[0] + L->e[i][1] * u[1] + L->e[i][2] * u[2];
+        const double eg = L->e[i][0] * grad[0] + L->e[i][1] * grad[1] + L->e[i][2] * grad[2];
+        const double quad = 1.5 * (eu * eu - usq / 3.0); /* 3/2 (e_a e_b - d_ab/3) u_a u_b */
+        feq[i] = 3.0 * t * (p0 - k * phi * lap + eu * rho + quad * rho) + k * t * (4.5 * eg * eg - 3.0 * g2);
+        geq[i] = 3.0 * t * (P->fe_gamma * mu + eu * phi + quad * phi);
+        fs += feq[i];
+        gs += geq[i];
+    }
+    feq[0] = rho - fs;
+    geq[0] = phi - gs;
+}
+
+void orc_fe_equilibria(const orc_params *P, double rho, double phi, const double *u, const double *grad,
+                       double lap, double *feq, double *geq) {
+    lattice_t L;
+    make_lattice(P->lattice, &L);
+    fe_equilibria(P, &L, rho, phi, u, grad, lap, feq, geq);
+}
+
+/* One free-energy node: hf, hg the (completed) populations as deviations from w; grad,
+ * lap of phi at the node.  LBGK on both lattices, tau_rho = tau_B + (phi + 1)/2
+ * (tau_A - tau_B) for f and tau_phi for g; the body force by the exact difference
+ * method on f. */
+static void fe_collide(const orc_params *P, const lattice_t *L, const double *hf, const double *hg,
+                       const double *grad, double lap, double *of, double *og) {
+    const int q = L->q;
+    double f[QMAX], g[QMAX], rho = 0.0, phi = 0.0, j[3] = {0, 0, 0};
+    for (int i = 0; i < q; i++) {
+        f[i] = L->w[i] + hf[i];
+        g[i] = L->w[i] + hg[i];
+        rho += f[i];
+        phi += g[i];
+        for (int a = 0; a < 3; a++) j[a] += L->e[i][a] * f[i];
+    }
+    double u[3], u1[3], v[3];
+    for (int a = 0; a < 3; a++) {
+        u[a] = j[a] / rho;
+        u1[a] = u[a] + P->g[a];        /* u + F/rho with F = rho g */
+        v[a] = u[a] + 0.5 * P->g[a];   /* (j + F/2) / rho */
+    }
+    double fe0[QMAX], fe1[QMAX], ge[QMAX], gdummy[QMAX], fdummy[QMAX];
+    fe_equilibria(P, L, rho, phi, u, grad, lap, fe0, gdummy);
+    fe_equilibria(P, L, rho, phi, u1, grad, lap, fe1, gdummy);
+    fe_equilibria(P, L, rho, phi, v, grad, lap, fdummy, ge);
+    const double tau_rho = P->tau_b + 0.5 * (phi + 1.0) * (P->tau - P->tau_b);
+    for (int i = 0; i < q; i++) {
+        const double fs = f[i] + (fe0[i] - f[i]) / tau_rho + (fe1[i] - fe0[i]);
+        const double gs = g[i] + (ge[i] - g[i]) / P->tau_phi;
+        of[i] = fs - L->w[i];
+        og[i] = gs - L->w[i];
+    }
+}
+
 int orc_init_eq(const orc_params *P, const double *rho, const double *u, const double *df, double *f) {
     if (check_params(P)) return -1;
     lattice_t L;
     make_lattice(P->lattice, &L);
     int64_t N = (int64_t)P->nx * P->ny * P->nz;
-    int C = P->model == ORC_SHANCHEN ? 2 : 1;
+    int C = ncomp_of(P);
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; n++) {
         double uu[3] = {0, 0, 0}, heq[QMAX];
         for (int a = 0; a < L.d; a++) uu[a] = u[a * N + n];
+        if (P->model == ORC_FREE_ENERGY) {
+            const double zero[3] = {0, 0, 0};
+            double fe[QMAX], ge[QMAX];
+            fe_equilibria(P, &L, rho[n], rho[N + n], uu, zero, 0.0, fe, ge);
+            for (int i = 0; i < L.q; i++) {
+                int64_t k0 = (int64_t)i * N + n, k1 = ((int64_t)L.q + i) * N + n;
+                f[k0] = fe[i] + (df ? df[k0] : 0.0);
+                f[k1] = ge[i] + (df ? df[k1] : 0.0);
+            }
+            continue;
+        }
         for (int c = 0; c < C; c++) {
             double drho = rho[c * N + n] - 1.0;
             if (P->model == ORC_ELBM) heq_entropic(&L, drho, uu, heq);
@@ -768,13 +882,14 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
     make_lattice(P->lattice, &L);
     const int q = L.q;
     const int64_t N = (int64_t)P->nx * P->ny * P->nz;
-    const int C = P->model == ORC_SHANCHEN ? 2 : 1;
-    if (C == 2 && flags)
+    const int C = ncomp_of(P);
+    const int FE = P->model == ORC_FREE_ENERGY;
+    if (P->model == ORC_SHANCHEN && flags)
         for (int64_t n = 0; n < N; n++)
             if (flags[n]) return -2; /* walls are not defined for the two-component model */
     if (flags)
         for (int64_t n = 0; n < N; n++)
-            if (flags[n] > 3 || (flags[n] >= 2 && P->model == ORC_ELBM)) return -2;
+            if (flags[n] > 3 || (flags[n] >= 2 && P->model == ORC_ELBM) || (flags[n] == 2 && FE)) return -2;
     double *cur = (double *)malloc(sizeof(double) * C * q * N);
     double *nxt = (double *)malloc(sizeof(double) * C * q * N);
     double *psi = C == 2 ? (double *)malloc(sizeof(double) * 2 * N) : NULL;
@@ -789,7 +904,23 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
     int64_t hist[32] = {0}, noconv = 0, nodes = 0;
 
     for (int t = 0; t < steps; t++) {
-        if (C == 2) {
+        if (FE) {
+            /* macroscopic pre-pass: every node's order parameter phi = sum_i g_i at time t
+             * (half-way nodes: of their completed set) */
+#pragma omp parallel for schedule(static)
+            for (int64_t n = 0; n < N; n++) {
+                int64_t x = n % P->nx, y = (n / P->nx) % P->ny, z = n / ((int64_t)P->nx * P->ny);
+                double hg[QMAX], r = 0.0;
+                for (int i = 0; i < q; i++) hg[i] = cur[((int64_t)q + i) * N + n];
+                if (flags && flags[n] == 3) {
+                    double hc[QMAX];
+                    complete_missing(P, &L, flags, x, y, z, hg, hc);
+                    memcpy(hg, hc, sizeof(double) * q);
+                }
+                for (int i = 0; i < q; i++) r += L.w[i] + hg[i];
+                psi[n] = r;
+            }
+        } else if (C == 2) {
             /* macroscopic pre-pass: every node's pseudopotential at time t */
 #pragma omp parallel for schedule(static)
             for (int64_t n = 0; n < N; n++)
@@ -810,6 +941,17 @@ int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc
                  * opposite direction instead of colliding (w_i = w_opp(i), so the same on h) */
                 for (int c = 0; c < C; c++)
                     for (int i = 0; i < q; i++) post[c][i] = hl[c][L.opp[i]];
+            } else if (FE) {
+                double grad[3], lap, hf[QMAX], hg[QMAX];
+                if (flags && flags[n] == 3) {
+                    complete_missing(P, &L, flags, x, y, z, hl[0], hf);
+                    complete_missing(P, &L, flags, x, y, z, hl[1], hg);
+                } else {
+                    memcpy(hf, hl[0], sizeof(double) * q);
+                    memcpy(hg, hl[1], sizeof(double) * q);
+                }
+                fe_stencil(P, &L, flags, psi, x, y, z, grad, &lap);
+                fe_collide(P, &L, hf, hg, grad, lap, post[0], post[1]);
             } else if (flags && flags[n] == 2) {
                 double drho = velocity_node_drho(P, &L, flags, x, y, z, hl[0]);
                 heq_poly(&L, drho, P->u_bc, post[0]);
@@ -878,9 +1020,10 @@ int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double
     make_lattice(P->lattice, &L);
     const int q = L.q;
     const int64_t N = (int64_t)P->nx * P->ny * P->nz;
-    const int C = P->model == ORC_SHANCHEN ? 2 : 1;
+    const int C = ncomp_of(P);
+    const int FE = P->model == ORC_FREE_ENERGY;
     double *psi = NULL;
-    if (C == 2) {
+    if (C == 2 && !FE) {
         psi = (double *)malloc(sizeof(double) * 2 * N);
         if (!psi) return -3;
         for (int64_t n = 0; n < N; n++)
@@ -896,7 +1039,7 @@ int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double
         double rc[2], jc[2][3], hl[QMAX], dr;
         for (int c = 0; c < C; c++) {
             for (int i = 0; i < q; i++) hl[i] = f[((int64_t)c * q + i) * N + n] - L.w[i];
-            if (flags && flags[n] == 3 && C == 1) {
+            if (flags && flags[n] == 3 && (C == 1 || FE)) {
                 double hc[QMAX];
                 complete_missing(P, &L, flags, x, y, z, hl, hc);
                 memcpy(hl, hc, sizeof(double) * q);
@@ -904,6 +1047,14 @@ int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double
             moments(&L, hl, &dr, jc[c]);
             rc[c] = 1.0 + dr;
             rho[c * N + n] = rc[c];
+        }
+        if (FE) {
+            /* rho[1] is phi; velocity (j + F/2)/rho of the f lattice, zero on walls */
+            double v[3] = {0, 0, 0};
+            if (!(flags && flags[n] == 1))
+                for (int a = 0; a < 3; a++) v[a] = (jc[0][a] + 0.5 * rc[0] * P->g[a]) / rc[0];
+            for (int a = 0; a < 3; a++) u[a * N + n] = v[a];
+            continue;
         }
         double v[3] = {0, 0, 0};
         if (flags && flags[n] == 2 && C == 1) {

@@ -16,7 +16,9 @@
  * Array layouts: populations f[C][Q][N], N = nx*ny*nz with x fastest
  * (node n = x + nx*(y + ny*z)); flags[N] (0 fluid, 1 full-way bounce-back wall,
  * 2 equilibrium velocity node with the velocity u_bc, 3 half-way bounce-back node);
- * densities rho[C][N]; velocities u[3][N] (the z row is zero on D2Q9).
+ * densities rho[C][N]; velocities u[3][N] (the z row is zero on D2Q9).  C = 2 for the
+ * Shan-Chen and free-energy models; for the latter component 1 is the order-parameter
+ * lattice g and rho[1] is phi.
  *
  * Parity unpinned (no printed values in the paper): the MRT, ELBM,
  * Shan-Chen, regularized and Smagorinsky steps beyond the identities and
@@ -31,7 +33,7 @@ extern "C" {
 #endif
 
 enum { ORC_D2Q9 = 0, ORC_D3Q19 = 1 };
-enum { ORC_BGK = 0, ORC_MRT = 1, ORC_ELBM = 2, ORC_SHANCHEN = 3, ORC_REG = 4, ORC_SMAG = 5 };
+enum { ORC_BGK = 0, ORC_MRT = 1, ORC_ELBM = 2, ORC_SHANCHEN = 3, ORC_REG = 4, ORC_SMAG = 5, ORC_FREE_ENERGY = 6 };
 
 typedef struct {
     int lattice, model;
@@ -47,6 +49,9 @@ typedef struct {
     int psi;              /* 0: psi = rho, 1: psi = 1 - exp(-rho) */
     double cs_smag;       /* Smagorinsky constant C_S (ORC_SMAG) */
     double u_bc[3];       /* velocity of the equilibrium velocity nodes (flag 2) */
+    /* free-energy binary model: tau is tau_A (phi = +1); populations f (density) and g
+     * (order parameter phi) are components 0 and 1 */
+    double tau_b, tau_phi, fe_a, fe_kappa, fe_gamma;
 } orc_params;
 
 typedef struct {
@@ -73,6 +78,13 @@ void orc_collide_node_sc(const orc_params *P, const double *f2, const double *ps
 int orc_init_eq(const orc_params *P, const double *rho, const double *u, const double *df, double *f);
 int orc_run(const orc_params *P, const uint8_t *flags, double *f, int steps, orc_stats *st);
 int orc_macro(const orc_params *P, const uint8_t *flags, const double *f, double *rho, double *u);
+/* Free-energy equilibria of one node (full populations, not shifted), given rho, phi,
+ * u[3], grad phi[3] and the Laplacian of phi. */
+void orc_fe_equilibria(const orc_params *P, double rho, double phi, const double *u, const double *grad,
+                       double lap, double *feq, double *geq);
+/* The gradient and Laplacian stencils at node (x, y, z) of a phi[N] field. */
+void orc_fe_stencil(const orc_params *P, const uint8_t *flags, const double *phi, int x, int y, int z,
+                    double *grad, double *lap);
 int orc_threads(void);
 void orc_set_threads(int n);
 

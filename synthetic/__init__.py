@@ -63,7 +63,7 @@ def uniform_pm(seed: int, stream: int, shape, amp: float, dtype=np.float64) -> n
 # ---------------------------------------------------------------------------
 # lattice identifiers shared with the C ABI (plain integers, no tables)
 D2Q9, D3Q19 = 0, 1
-BGK, MRT, ELBM, SHANCHEN, REG, SMAG = 0, 1, 2, 3, 4, 5
+BGK, MRT, ELBM, SHANCHEN, REG, SMAG, FREE_ENERGY = 0, 1, 2, 3, 4, 5, 6
 FLUID, WALL, VELOCITY, HALFWAY = 0, 1, 2, 3
 Q_OF = {D2Q9: 9, D3Q19: 19}
 D_OF = {D2Q9: 2, D3Q19: 3}
@@ -95,6 +95,7 @@ class Case:
     psi: int = 0
     cs_smag: float = 0.1
     u_bc: tuple = (0.0, 0.0, 0.0)
+    fe: dict | None = None   # free-energy model: tau_b, tau_phi, a, kappa, gamma (tau is tau_A)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -111,7 +112,7 @@ class Case:
 
     @property
     def ncomp(self) -> int:
-        return 2 if self.model == SHANCHEN else 1
+        return 2 if self.model in (SHANCHEN, FREE_ENERGY) else 1
 
 
 def _grid(nx, ny, nz):
@@ -295,6 +296,37 @@ def lid_driven_cavity(n=254, model=BGK, re=1000.0, u_lid=0.05, steps=1000, mrt_s
     return Case("d3q19_ldc_%d_re%g" % (n, re), D3Q19, model, n, n, n, tau, (0.0, 0.0, 0.0), steps,
                 cavity_flags(n, n, n), rho, u, mrt_rates=rates, cs_smag=cs_smag, u_bc=(0.0, u_lid, 0.0),
                 extra={"re": re, "u_lid": u_lid})
+
+
+def binary_poiseuille(nx=64, ny=256, g=2e-7, nu0=1.0 / 6.0, nu1=1.0 / 24.0, kappa=1e-4, a=32e-4, gamma=25.0,
+                      tau_phi=1.0, steps=0):
+    """The paper's binary Poiseuille flow (free-energy model): D2Q9 channel along x with
+    dry walls on y = 0, ny - 1 and half-way bounce-back nodes on y = 1, ny - 2; the core
+    |y - yc| <= L/2 holds the fluid of viscosity nu1 (phi = +1, tau_A), the outer layers
+    nu0 (phi = -1, tau_B); body force g along x; at rest.  yc = (ny - 1)/2 and L = yc - 1
+    (the wall half a node beyond the wet node)."""
+    yc = (ny - 1) / 2.0
+    L = yc - 1.0
+    _, y, _ = _grid(nx, ny, 1)
+    phi = np.where(np.abs(y - yc) <= L / 2, 1.0, -1.0)
+    rho = np.vstack([np.ones(nx * ny), phi])
+    u = np.zeros((2, nx * ny))
+    fe = {"tau_b": tau_from_nu(nu0), "tau_phi": tau_phi, "a": a, "kappa": kappa, "gamma": gamma}
+    return Case("d2q9_binary_poiseuille_%dx%d" % (nx, ny), D2Q9, FREE_ENERGY, nx, ny, 1, tau_from_nu(nu1),
+                (g, 0.0, 0.0), steps, halfway_channel_flags_2d(nx, ny), rho, u, fe=fe,
+                extra={"yc": yc, "L": L, "nu0": nu0, "nu1": nu1, "g": g})
+
+
+def spinodal(nx=254, ny=100, nz=100, amp=0.01, seed=DEFAULT_SEED, a=0.04, kappa=0.04, gamma=1.0, tau=1.0,
+             steps=0):
+    """Spinodal decomposition (the paper's binary-fluid benchmark): D3Q19 free-energy
+    model, periodic, rho = 1, phi = U(-amp, amp) seeded, at rest."""
+    n = nx * ny * nz
+    phi = uniform_pm(seed, 3, (n,), amp)
+    rho = np.vstack([np.ones(n), phi])
+    fe = {"tau_b": tau, "tau_phi": tau, "a": a, "kappa": kappa, "gamma": gamma}
+    return Case("d3q19_spinodal_%dx%dx%d" % (nx, ny, nz), D3Q19, FREE_ENERGY, nx, ny, nz, tau, (0.0, 0.0, 0.0),
+                steps, None, rho, np.zeros((3, n)), fe=fe)
 
 
 def c5_shan_chen(n=384, steps=2000, G=0.9, amp=0.01, seed=DEFAULT_SEED, tau=1.0):
