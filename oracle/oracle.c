@@ -827,13 +827,29 @@ static void fe_collide(const orc_params *P, const lattice_t *L, const double *hf
         u1[a] = u[a] + P->g[a];        /* u + F/rho with F = rho g */
         v[a] = u[a] + 0.5 * P->g[a];   /* (j + F/2) / rho */
     }
-    double fe0[QMAX], fe1[QMAX], ge[QMAX], gdummy[QMAX], fdummy[QMAX];
+    double fe0[QMAX], ge[QMAX], gdummy[QMAX], fdummy[QMAX], edm[QMAX];
     fe_equilibria(P, L, rho, phi, u, grad, lap, fe0, gdummy);
-    fe_equilibria(P, L, rho, phi, u1, grad, lap, fe1, gdummy);
     fe_equilibria(P, L, rho, phi, v, grad, lap, fdummy, ge);
+    /* feq(u1) - feq(u): only 3 t_i rho (e.u + 3/2 ((e.u)^2 - u^2/3)) depends on u, so with
+     * a = u1 - u the difference is 3 t_i rho (e.a + 3/2 (e.a (2 e.u + e.a) - a.(2u + a)/3)),
+     * and the rest population takes minus the sum.  Written out this way the O(F) term
+     * keeps its precision; as a difference of two O(1) equilibria it would not. */
+    double es = 0.0;
+    for (int i = 1; i < q; i++) {
+        double ea = 0.0, eu = 0.0, a2 = 0.0;
+        for (int a = 0; a < 3; a++) {
+            const double aa = u1[a] - u[a];
+            ea += L->e[i][a] * aa;
+            eu += L->e[i][a] * u[a];
+            a2 += aa * (2.0 * u[a] + aa);
+        }
+        edm[i] = 3.0 * L->w[i] * rho * (ea + 1.5 * (ea * (2.0 * eu + ea) - a2 / 3.0));
+        es += edm[i];
+    }
+    edm[0] = -es;
     const double tau_rho = P->tau_b + 0.5 * (phi + 1.0) * (P->tau - P->tau_b);
     for (int i = 0; i < q; i++) {
-        const double fs = f[i] + (fe0[i] - f[i]) / tau_rho + (fe1[i] - fe0[i]);
+        const double fs = f[i] + (fe0[i] - f[i]) / tau_rho + edm[i];
         const double gs = g[i] + (ge[i] - g[i]) / P->tau_phi;
         of[i] = fs - L->w[i];
         og[i] = gs - L->w[i];

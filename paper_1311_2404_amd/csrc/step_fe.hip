@@ -1,0 +1,212 @@
+// Free-energy binary model (free energy model subsection): the order-parameter pre-pass
+// and the step of both lattices (f: density, g: order parameter phi).
+//
+// Equilibria, for the non-rest populations (lattice weights t_i):
+//   f_i = 3 t_i (p0 - kappa phi lap + rho e.u + 3/2 rho ((e.u)^2 - u^2/3))
+//         + kappa t_i (4.5 (e.grad)^2 - 3 |grad|^2)
+//   g_i = 3 t_i (Gamma mu + phi e.u + 3/2 phi ((e.u)^2 - u^2/3))
+// with p0 = rho/3 + A(-phi^2/2 + 3 phi^4/4), mu = A(-phi + phi^3) - kappa lap; the rest
+// populations take what mass leaves (f_0 = rho - sum, g_0 = phi - sum).  These weights
+// meet the moment conditions the subsection states (second moment of f = the pressure
+// tensor + rho u u).  grad and lap use the isotropic lattice-weight stencils on the phi
+// field of the pre-pass; a wall neighbour contributes the node's own phi (neutral
+// wetting).  f relaxes with tau_rho = tau_B + (phi + 1)/2 (tau_A - tau_B) and takes the
+// body force by the exact difference method around u = j/rho; g relaxes with tau_phi
+// towards its equilibrium at the velocity (j + F/2)/rho.  Stored values are plain
+// (unshifted) f and g.
+#include "dispatch.hpp"
+#include "step.hpp"
+
+namespace lbm {
+
+namespace {
+
+// half-way bounce-back completion of a population set (missing ones from wall nodes take
+// the opposite population of the node)
+template <class L, class C>
+__device__ __forceinline__ void fe_complete(C *v, const StepParams &p, const Geo &g) {
+    C b[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) b[i] = v[i];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+        if (p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1) v[i] = b[opp(i)];
+}
+
+// phi = sum_i g_i of the populations streaming into x (completed on half-way nodes)
+template <class L, class St, int LAYOUT, bool FLAGS>
+__global__ __launch_bounds__(256) void k_fe_phi(StepParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    static_assert(!St::shifted, "the free-energy kernels keep plain f and g");
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+    const uint32_t n = g.at(0, 0, 0);
+    const T *gs = static_cast<const T *>(p.src) + size_t(L::Q) * p.S;
+    C v[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        int slot, dx, dy, dz;
+        canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+        v[i] = C(*pop_addr(gs, p.S, slot, g, dx, dy, dz));
+    }
+    if (FLAGS && p.flags[n] == 3) fe_complete<L, C>(v, p, g);
+    C r = C(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) r += v[i];
+    static_cast<C *>(const_cast<void *>(p.psi))[n] = r;
+}
+
+template <class L, class St, int LAYOUT, bool FLAGS>
+__global__ __launch_bounds__(256) void k_step_fe(StepParams p) {
+    using T = typename St::T;
+    using C = typename St::C;
+    constexpr int Q = L::Q;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+    const uint32_t n = g.at(0, 0, 0), S = p.S;
+    const T *src = static_cast<const T *>(p.src);
+    T *dst = static_cast<T *>(p.dst);
+    const C *__restrict__ phis = static_cast<const C *>(p.psi);
+    C f[Q], gg[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        int slot, dx, dy, dz;
+        canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+        f[i] = C(LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i));
+        gg[i] = C(LBM_LOAD(pop_addr(src, S, Q + slot, g, dx, dy, dz), i));
+    }
+    const uint32_t fl = FLAGS ? p.flags[n] : 0u;
+    if (fl == 1u) {
+        // full-way bounce-back on both lattices
+        C t[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) t[i] = f[opp(i)];
+#pragma unroll
+        for (int i = 0; i < Q; i++) f[i] = t[i];
+#pragma unroll
+        for (int i = 0; i < Q; i++) t[i] = gg[opp(i)];
+#pragma unroll
+        for (int i = 0; i < Q; i++) gg[i] = t[i];
+    } else {
+        if (FLAGS && fl == 3u) {
+            fe_complete<L, C>(f, p, g);
+            fe_complete<L, C>(gg, p, g);
+        }
+        C rho = C(0), phi = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            rho += f[i];
+            phi += gg[i];
+            jx += C(L::ex(i)) * f[i];
+            jy += C(L::ey(i)) * f[i];
+            jz += C(L::ez(i)) * f[i];
+        }
+        // stencils on the pre-pass phi field
+        const C p0x = phis[n];
+        C gx = C(0), gy = C(0), gz = C(0), lap = C(0);
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            const uint32_t m = g.at(L::ex(i), L::ey(i), L::ez(i));
+            const C pn = (FLAGS && p.flags[m] == 1) ? p0x : phis[m];
+            const C tw = C(3 * L::w(i)) * pn;
+            gx += C(L::ex(i)) * tw;
+            gy += C(L::ey(i)) * tw;
+            gz += C(L::ez(i)) * tw;
+            lap += C(6 * L::w(i)) * (pn - p0x);
+        }
+        const C A = C(p.fe_a), kap = C(p.fe_kappa);
+        const C mu = A * (-phi + phi * phi * phi) - kap * lap;
+        const C pb = rho * C(1.0 / 3.0) + A * (C(-0.5) * phi * phi + C(0.75) * phi * phi * phi * phi);
+        const C iso = pb - kap * phi * lap;
+        const C g2 = gx * gx + gy * gy + gz * gz;
+        const C ax = C(p.g[0]), ay = C(p.g[1]), az = C(L::D == 3 ? p.g[2] : 0.0);
+        const C irho = C(1) / rho;
+        const C ux = jx * irho, uy = jy * irho, uz = jz * irho;
+        const C u1x = ux + ax, u1y = uy + ay, u1z = uz + az;
+        const C vx = ux + C(0.5) * ax, vy = uy + C(0.5) * ay, vz = uz + C(0.5) * az;
+        const C usq = ux * ux + uy * uy + uz * uz, u1sq = u1x * u1x + u1y * u1y + u1z * u1z;
+        const C vsq = vx * vx + vy * vy + vz * vz;
+        const C itr = C(1) / (C(p.tau_b) + C(0.5) * (phi + C(1)) * (C(p.tau_a) - C(p.tau_b)));
+        const C itp = C(1) / C(p.tau_phi);
+        const C gmu = C(p.fe_gamma) * mu;
+        C s0 = C(0), s1 = C(0), sg = C(0);
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            const C t3 = C(3 * L::w(i));
+            const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
+            const C eu1 = C(L::ex(i)) * u1x + C(L::ey(i)) * u1y + C(L::ez(i)) * u1z;
+            const C ev = C(L::ex(i)) * vx + C(L::ey(i)) * vy + C(L::ez(i)) * vz;
+            const C eg = C(L::ex(i)) * gx + C(L::ey(i)) * gy + C(L::ez(i)) * gz;
+            const C grad_t = kap * C(L::w(i)) * (C(4.5) * eg * eg - C(3) * g2);
+            const C fe0 = t3 * (iso + eu * rho + C(1.5) * (eu * eu - usq * C(1.0 / 3.0)) * rho) + grad_t;
+            const C fe1 = t3 * (iso + eu1 * rho + C(1.5) * (eu1 * eu1 - u1sq * C(1.0 / 3.0)) * rho) + grad_t;
+            const C ge = t3 * (gmu + ev * phi + C(1.5) * (ev * ev - vsq * C(1.0 / 3.0)) * phi);
+            s0 += fe0;
+            s1 += fe1;
+            sg += ge;
+            f[i] = f[i] + (fe0 - f[i]) * itr + (fe1 - fe0);
+            gg[i] = gg[i] + (ge - gg[i]) * itp;
+        }
+        const C fe0r = rho - s0, fe1r = rho - s1, ger = phi - sg;
+        f[0] = f[0] + (fe0r - f[0]) * itr + (fe1r - fe0r);
+        gg[0] = gg[0] + (ger - gg[0]) * itp;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        int slot, dx, dy, dz;
+        post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+        LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), T(f[i]));
+        LBM_STORE(pop_addr(dst, S, Q + slot, g, dx, dy, dz), T(gg[i]));
+    }
+}
+
+template <class F>
+hipError_t with_fe_storage(int storage, F &&fn) {
+    switch (storage) {
+    case ST_F64: return fn(StF64{});
+    case ST_F32: return fn(StF32{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fe_phi(int lattice, int storage, int layout, bool flags, const StepParams &p, const LaunchCfg &c) {
+    return with_lattice(lattice, [&](auto lt) {
+        using L = decltype(lt);
+        return with_fe_storage(storage, [&](auto st) {
+            using St = decltype(st);
+            return with_layout(layout, [&](auto lay) {
+                constexpr int LAY = decltype(lay)::value;
+                if (flags) k_fe_phi<L, St, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
+                else k_fe_phi<L, St, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                return hipGetLastError();
+            });
+        });
+    });
+}
+
+hipError_t launch_step_fe(int lattice, int storage, int layout, bool flags, const StepParams &p,
+                          const LaunchCfg &c) {
+    return with_lattice(lattice, [&](auto lt) {
+        using L = decltype(lt);
+        return with_fe_storage(storage, [&](auto st) {
+            using St = decltype(st);
+            return with_layout(layout, [&](auto lay) {
+                constexpr int LAY = decltype(lay)::value;
+                if (flags) k_step_fe<L, St, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
+                else k_step_fe<L, St, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                return hipGetLastError();
+            });
+        });
+    });
+}
+
+}  // namespace lbm

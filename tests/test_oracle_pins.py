@@ -1173,3 +1173,32 @@ def test_free_energy_stencil_neutral_wetting():
             l_ref += 6 * w[i] * (pn - phi[0, 3, x])
         np.testing.assert_allclose(grad, g_ref, rtol=0, atol=1e-14)
         assert abs(lap - l_ref) < 1e-14
+
+
+@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
+def test_free_energy_single_node_step(lattice):
+    """On a one-node periodic lattice the stencils vanish and every population streams
+    back to the node, so one step is the collision alone: f + (feq(u) - f)/tau_rho +
+    (feq(u + a) - feq(u)) with u = j/rho, tau_rho = tau_B + (phi + 1)/2 (tau_A - tau_B), and
+    g + (geq(u + a/2) - g)/tau_phi, the equilibria being the ones pinned above."""
+    d = _d(lattice)
+    acc = (2e-3, -1e-3, 1.5e-3 if d == 3 else 0.0)
+    tau_a = 0.8
+    o = oracle.Oracle(lattice, S.FREE_ENERGY, 1, 1, 1, tau_a, acc, fe=FE_PARAMS)
+    e, w, _ = oracle.tables(lattice)
+    rng = np.random.default_rng(71)
+    f0 = w * (1 + 0.3 * (2 * rng.random(len(w)) - 1))
+    g0 = w * 0.4 * (2 * rng.random(len(w)) - 1)
+    o.set_f(np.vstack([f0, g0])[:, :, None])
+    o.run(1)
+    rho, phi = f0.sum(), g0.sum()
+    u = np.zeros(3)
+    u[:d] = (e[:, :d].T @ f0) / rho
+    a = np.array(acc)
+    zero = np.zeros(3)
+    fe0, _ = o.fe_equilibria(rho, phi, u, zero, 0.0)
+    fe1, _ = o.fe_equilibria(rho, phi, u + a, zero, 0.0)
+    _, ge = o.fe_equilibria(rho, phi, u + a / 2, zero, 0.0)
+    tau_rho = FE_PARAMS["tau_b"] + 0.5 * (phi + 1) * (tau_a - FE_PARAMS["tau_b"])
+    np.testing.assert_allclose(o.f[0, :, 0], f0 + (fe0 - f0) / tau_rho + (fe1 - fe0), rtol=0, atol=2e-16)
+    np.testing.assert_allclose(o.f[1, :, 0], g0 + (ge - g0) / FE_PARAMS["tau_phi"], rtol=0, atol=2e-16)
