@@ -48,8 +48,12 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
  * (the non-equilibrium part replaced by its second-order projection w_i/(2 cs^4)
  * (e_i e_i - cs^2 I):Pi_neq before relaxing; regularized-LBM subsection) and
  * Smagorinsky LBGK (local tau = tau0 + tau_t from the momentum flux of f - feq,
- * Smagorinsky-subgrid equations). */
-enum { LBM_BGK = 0, LBM_MRT = 1, LBM_ELBM = 2, LBM_SHANCHEN = 3, LBM_REGULARIZED = 4, LBM_SMAGORINSKY = 5 };
+ * Smagorinsky-subgrid equations), and the free-energy binary fluid (free energy model
+ * subsection: a density lattice f and an order-parameter lattice g, C = 2, with the
+ * chemical potential, the pressure tensor and the gradient stencils; see
+ * lbm_set_free_energy). */
+enum { LBM_BGK = 0, LBM_MRT = 1, LBM_ELBM = 2, LBM_SHANCHEN = 3, LBM_REGULARIZED = 4, LBM_SMAGORINSKY = 5,
+       LBM_FREE_ENERGY = 6 };
 /* Storage of the populations in HBM.  S = shifted: the stored value is f_i - w_i (the
  * round-off minimising formulation of the precision subsection); compute is FP32 for
  * every storage except F64. */
@@ -106,6 +110,20 @@ int lbm_set_elbm(lbm_sim *sim, int alpha_init, double tol, int max_iter);
  * 1: 1 - exp(-rho)).  Default G = 0, psi = 0. */
 int lbm_set_shanchen(lbm_sim *sim, double G, int psi);
 
+/* LBM_FREE_ENERGY parameters: f relaxes with tau_rho = tau_B + (phi + 1)/2 (tau - tau_B)
+ * (tau from lbm_create is tau_A, the relaxation time where phi = +1), g with tau_phi;
+ * free energy A (bulk) and kappa (interface), mobility parameter Gamma.  The equilibria
+ * give the second moments the subsection requires (pressure tensor with bulk pressure
+ * rho/3 + A(-phi^2/2 + 3 phi^4/4) and chemical potential A(-phi + phi^3) - kappa lap phi),
+ * with isotropic lattice-weight gradient and Laplacian stencils; a wall neighbour enters
+ * them with the node's own phi.  The body force acts on f by the exact difference method.
+ * Populations: f is component 0, g component 1; lbm_init_eq's rho[1] and lbm_macro's
+ * rho[1] are phi; the velocity is (j_f + F/2)/rho.  Storage F64, F32 or shifted F32
+ * (the step works on f - w; shifted storage keeps small forces, see the tests).  Default
+ * tau_B = tau, tau_phi = 1, A = 0.04, kappa = 0.04, Gamma = 1; other models:
+ * LBM_EUNSUPPORTED. */
+int lbm_set_free_energy(lbm_sim *sim, double tau_b, double tau_phi, double a, double kappa, double gamma);
+
 /* Velocity u[3] of every LBM_VELOCITY node (u[2] ignored on D2Q9); default 0.  The
  * macroscopic output of such a node is the density of its completed set and this
  * velocity.  Velocity nodes are accepted by lbm_set_flags for LBM_BGK, LBM_MRT,
@@ -126,7 +144,7 @@ int lbm_set_stream(lbm_sim *sim, void *hip_stream);
 /* Node flags, host array uint8[N] (LBM_FLUID / LBM_WALL_BB / LBM_VELOCITY /
  * LBM_HALFWAY_BB), copied.  Before or after init.  Values above 3: LBM_EINVAL.  Walls
  * are not supported with LBM_SHANCHEN, velocity and half-way nodes not with LBM_SHANCHEN
- * or LBM_ELBM (LBM_EUNSUPPORTED).  The macroscopic output of a half-way node is that of
+ * or LBM_ELBM, velocity nodes not with LBM_FREE_ENERGY (LBM_EUNSUPPORTED).  The macroscopic output of a half-way node is that of
  * its completed population set. */
 int lbm_set_flags(lbm_sim *sim, const uint8_t *flags);
 

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_D2Q9, LBM_D3Q19 = 0, 1
-LBM_BGK, LBM_MRT, LBM_ELBM, LBM_SHANCHEN, LBM_REGULARIZED, LBM_SMAGORINSKY = 0, 1, 2, 3, 4, 5
+LBM_BGK, LBM_MRT, LBM_ELBM, LBM_SHANCHEN, LBM_REGULARIZED, LBM_SMAGORINSKY, LBM_FREE_ENERGY = 0, 1, 2, 3, 4, 5, 6
 LBM_F64, LBM_F32, LBM_F32S, LBM_BF16S, LBM_F16S = 0, 1, 2, 3, 4
 LBM_AB, LBM_AA = 0, 1
 LBM_FLUID, LBM_WALL_BB, LBM_VELOCITY, LBM_HALFWAY_BB = 0, 1, 2, 3
@@ -37,6 +37,7 @@ _SIGS = [
     ("lbm_set_elbm", C.c_int, [_vp, C.c_int, C.c_double, C.c_int]),
     ("lbm_set_shanchen", C.c_int, [_vp, C.c_double, C.c_int]),
     ("lbm_set_velocity_bc", C.c_int, [_vp, _dp]),
+    ("lbm_set_free_energy", C.c_int, [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]),
     ("lbm_set_smagorinsky", C.c_int, [_vp, C.c_double]),
     ("lbm_set_stream", C.c_int, [_vp, _vp]),
     ("lbm_set_flags", C.c_int, [_vp, C.POINTER(C.c_uint8)]),
@@ -144,6 +145,10 @@ def lbm_set_elbm(sim, alpha_init=0, tol=1e-10, max_iter=20):
 
 def lbm_set_shanchen(sim, G, psi=0):
     _err(sim, lib().lbm_set_shanchen(sim, G, psi))
+
+
+def lbm_set_free_energy(sim, tau_b, tau_phi, a, kappa, gamma):
+    _err(sim, lib().lbm_set_free_energy(sim, tau_b, tau_phi, a, kappa, gamma))
 
 
 def lbm_set_velocity_bc(sim, u):
@@ -296,7 +301,7 @@ class Sim:
         self.nx, self.ny, self.nz = nx, ny, nz
         self.q = 9 if lattice == LBM_D2Q9 else 19
         self.d = 2 if lattice == LBM_D2Q9 else 3
-        self.ncomp = 2 if model == LBM_SHANCHEN else 1
+        self.ncomp = 2 if model in (LBM_SHANCHEN, LBM_FREE_ENERGY) else 1
         self.n = nx * ny * nz
         self.storage = storage
         self.h = lbm_create(lattice, model, nx, ny, nz, tau, force)
@@ -318,6 +323,9 @@ class Sim:
             lbm_set_shanchen(s.h, case.G, case.psi)
         if case.model == LBM_SMAGORINSKY:
             lbm_set_smagorinsky(s.h, case.cs_smag)
+        if case.model == LBM_FREE_ENERGY:
+            fe = case.fe
+            lbm_set_free_energy(s.h, fe["tau_b"], fe["tau_phi"], fe["a"], fe["kappa"], fe["gamma"])
         if case.flags is not None:
             lbm_set_flags(s.h, case.flags)
         if any(case.u_bc):

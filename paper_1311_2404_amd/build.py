@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "liblbm.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["step_bgk.hip", "step_mrt.hip", "step_elbm.hip", "step_sc.hip", "step_reg.hip", "step_smag.hip",
-           "aux.hip", "mlp.hip", "api.cpp"]
+           "step_fe.hip", "aux.hip", "mlp.hip", "api.cpp"]
 
 # -packed-fp32-ops: no packed FP32 (v_pk_*_f32) instructions in device code.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-function",

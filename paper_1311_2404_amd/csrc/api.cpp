@@ -34,6 +34,8 @@ struct lbm_sim {
     int psi_mode = 0;
     double cs_smag = 0.1;  // Smagorinsky constant
     double u_bc[3] = {0.0, 0.0, 0.0};  // velocity of the equilibrium velocity nodes
+    // free-energy model: tau_B, tau_phi, A, kappa, Gamma (tau is tau_A)
+    double fe_tau_b = 1.0, fe_tau_phi = 1.0, fe_a = 0.04, fe_kappa = 0.04, fe_gamma = 1.0;
     hipStream_t stream = nullptr;
     int device = 0;
     void *buf[2] = {nullptr, nullptr};
@@ -142,6 +144,12 @@ StepParams base_params(const lbm_sim *s) {
     for (int k = 0; k < 19; k++) p.s[k] = s->s[k];
     for (int a = 0; a < 3; a++) p.u_bc[a] = s->u_bc[a];
     p.tau0 = s->tau;
+    p.tau_a = s->tau;
+    p.tau_b = s->fe_tau_b;
+    p.tau_phi = s->fe_tau_phi;
+    p.fe_a = s->fe_a;
+    p.fe_kappa = s->fe_kappa;
+    p.fe_gamma = s->fe_gamma;
     p.smag_k = 36.0 * s->cs_smag * s->cs_smag;
     p.beta = 0.5 / s->tau;
     p.alpha_tol = s->alpha_tol;
@@ -224,7 +232,8 @@ int ensure_alloc(lbm_sim *s) {
     HIPCHK(s, hipMalloc(&s->buf[0], bytes));
     if (s->layout == LBM_AB) HIPCHK(s, hipMalloc(&s->buf[1], bytes));
     HIPCHK(s, hipMalloc(&s->stage, sizeof(double) * s->N));
-    if (s->model == LBM_SHANCHEN) HIPCHK(s, hipMalloc(&s->psi_d, 2 * size_t(s->N) * compute_size(s->storage)));
+    if (s->model == LBM_SHANCHEN || s->model == LBM_FREE_ENERGY)
+        HIPCHK(s, hipMalloc(&s->psi_d, 2 * size_t(s->N) * compute_size(s->storage)));
     HIPCHK(s, hipMalloc(&s->bad_d, sizeof(unsigned int)));
     HIPCHK(s, hipMalloc(&s->stats_d, sizeof(unsigned long long) * (NEWTON_BINS + 1)));
     HIPCHK(s, hipMemsetAsync(s->stats_d, 0, sizeof(unsigned long long) * (NEWTON_BINS + 1), s->stream));
@@ -312,7 +321,7 @@ int lbm_create(int lattice, int model, int nx, int ny, int nz, double tau, const
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
     *out = nullptr;
     if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(nullptr, LBM_EINVAL, "unknown lattice");
-    if (model < LBM_BGK || model > LBM_SMAGORINSKY) return fail(nullptr, LBM_EINVAL, "unknown model");
+    if (model < LBM_BGK || model > LBM_FREE_ENERGY) return fail(nullptr, LBM_EINVAL, "unknown model");
     if (nx <= 0 || ny <= 0 || nz <= 0) return fail(nullptr, LBM_EINVAL, "grid sizes must be positive");
     if (lattice == LBM_D2Q9 && nz != 1) return fail(nullptr, LBM_EINVAL, "D2Q9 needs nz == 1");
     if (nz > 65535 || ny > 65535) return fail(nullptr, LBM_EINVAL, "ny and nz must be <= 65535");
@@ -339,7 +348,8 @@ int lbm_create(int lattice, int model, int nx, int ny, int nz, double tau, const
     s->nz = nz;
     s->Q = lattice == LBM_D2Q9 ? 9 : 19;
     s->D = lattice == LBM_D2Q9 ? 2 : 3;
-    s->C = model == LBM_SHANCHEN ? 2 : 1;
+    s->C = model == LBM_SHANCHEN || model == LBM_FREE_ENERGY ? 2 : 1;
+    s->fe_tau_b = tau;
     s->N = uint32_t(Nd);
     s->tau = tau;
     for (int a = 0; a < 3; a++) s->g[a] = g[a];
@@ -357,8 +367,10 @@ int lbm_set_storage(lbm_sim *s, int storage, int layout, int stochastic_round) {
     if (layout != LBM_AB && layout != LBM_AA) return fail(s, LBM_EINVAL, "unknown layout");
     if (stochastic_round && storage != LBM_BF16S && storage != LBM_F16S)
         return fail(s, LBM_EINVAL, "stochastic rounding applies to BF16S/F16S only");
-    if (stochastic_round && (s->model == LBM_ELBM || s->model == LBM_SHANCHEN))
+    if (stochastic_round && (s->model == LBM_ELBM || s->model == LBM_SHANCHEN || s->model == LBM_FREE_ENERGY))
         return fail(s, LBM_EUNSUPPORTED, "stochastic rounding is built for BGK and MRT");
+    if (s->model == LBM_FREE_ENERGY && storage != LBM_F64 && storage != LBM_F32 && storage != LBM_F32S)
+        return fail(s, LBM_EUNSUPPORTED, "the free-energy model keeps F64, F32 or shifted F32 populations");
     s->storage = storage;
     s->layout = layout;
     s->sr = stochastic_round ? 1 : 0;
@@ -390,6 +402,21 @@ int lbm_set_shanchen(lbm_sim *s, double G, int psi) {
     if (!std::isfinite(G) || (psi != 0 && psi != 1)) return fail(s, LBM_EINVAL, "bad G or psi");
     s->G = G;
     s->psi_mode = psi;
+    return LBM_OK;
+}
+
+int lbm_set_free_energy(lbm_sim *s, double tau_b, double tau_phi, double a, double kappa, double gamma) {
+    if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
+    if (s->model != LBM_FREE_ENERGY) return fail(s, LBM_EUNSUPPORTED, "the parameters belong to the free-energy model");
+    if (!(tau_b > 0.5) || !(tau_phi > 0.5) || !std::isfinite(tau_b) || !std::isfinite(tau_phi))
+        return fail(s, LBM_EINVAL, "tau_B and tau_phi must be finite and > 1/2");
+    if (!std::isfinite(a) || !std::isfinite(kappa) || !std::isfinite(gamma) || kappa < 0.0 || gamma < 0.0)
+        return fail(s, LBM_EINVAL, "A must be finite, kappa and Gamma finite and >= 0");
+    s->fe_tau_b = tau_b;
+    s->fe_tau_phi = tau_phi;
+    s->fe_a = a;
+    s->fe_kappa = kappa;
+    s->fe_gamma = gamma;
     return LBM_OK;
 }
 
@@ -430,6 +457,10 @@ int lbm_set_flags(lbm_sim *s, const uint8_t *flags) {
         return fail(s, LBM_EUNSUPPORTED, "walls are not supported with the Shan-Chen model");
     if (vel && s->model == LBM_ELBM)
         return fail(s, LBM_EUNSUPPORTED, "boundary nodes are built for the polynomial-equilibrium models");
+    if (s->model == LBM_FREE_ENERGY)
+        for (uint32_t n = 0; n < s->N; n++)
+            if (flags[n] == LBM_VELOCITY)
+                return fail(s, LBM_EUNSUPPORTED, "velocity nodes are not built for the free-energy model");
     HIPCHK(s, hipSetDevice(s->device));
     if (!s->flags_d) HIPCHK(s, hipMalloc(&s->flags_d, s->N));
     HIPCHK(s, hipMemcpyAsync(s->flags_d, flags, s->N, hipMemcpyHostToDevice, s->stream));
@@ -460,6 +491,14 @@ int lbm_init_eq(lbm_sim *s, const double *rho, const double *u, const double *df
             p.rho = rho_d + size_t(c) * N;
             p.u = u_d;
             p.entropic = s->model == LBM_ELBM;
+            if (s->model == LBM_FREE_ENERGY) {
+                // rho[0] is rho, rho[1] is phi; both lattices start at their equilibria
+                p.fe = 1;
+                p.rho = rho_d;
+                p.phi = rho_d + N;
+                p.fe_a = s->fe_a;
+                p.fe_gamma = s->fe_gamma;
+            }
             if (df) {
                 HIPCHK(s, hipMemcpyAsync(s->stage, df + (size_t(c) * s->Q + q) * N, sizeof(double) * N,
                                          hipMemcpyHostToDevice, s->stream));
@@ -528,6 +567,10 @@ int lbm_step(lbm_sim *s, int n) {
         case LBM_REGULARIZED: e = launch_step_reg(s->lattice, s->storage, s->sr, lay, flag_mode(s), p, cfg); break;
         case LBM_SMAGORINSKY: e = launch_step_smag(s->lattice, s->storage, s->sr, lay, flag_mode(s), p, cfg); break;
         case LBM_ELBM: e = launch_step_elbm(s->lattice, s->storage, lay, flag_mode(s), p, cfg); break;
+        case LBM_FREE_ENERGY:
+            e = launch_fe_phi(s->lattice, s->storage, lay, s->has_walls, p, cfg);
+            if (e == hipSuccess) e = launch_step_fe(s->lattice, s->storage, lay, s->has_walls, p, cfg);
+            break;
         default:
             e = launch_psi(s->lattice, s->storage, lay, p, cfg);
             if (e == hipSuccess) e = launch_step_sc(s->lattice, s->storage, lay, p, cfg);
@@ -576,7 +619,8 @@ int lbm_diag(lbm_sim *s, double out[8]) {
     double *rd = s->macro_d, *ud = s->macro_d + size_t(s->C) * s->N;
     rc = macro_into(s, rd, ud, 1, nullptr);
     if (rc) return rc;
-    HIPCHK(s, launch_diag_reduce(rd, ud, s->N, s->C, s->red_d, nblocks, s->red_d + size_t(nblocks) * 8, s->stream));
+    HIPCHK(s, launch_diag_reduce(rd, ud, s->N, s->C, s->model == LBM_FREE_ENERGY, s->red_d, nblocks,
+                                 s->red_d + size_t(nblocks) * 8, s->stream));
     HIPCHK(s, hipMemcpyAsync(out, s->red_d + size_t(nblocks) * 8, sizeof(double) * 8, hipMemcpyDeviceToHost,
                              s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));

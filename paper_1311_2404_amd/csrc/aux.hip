@@ -40,6 +40,29 @@ __device__ double heq_plane(int q, double rho, double ux, double uy, double uz, 
     return r;
 }
 
+// Free-energy equilibrium (zero phi gradients) of population q of the f lattice (comp 0)
+// or the g lattice (comp 1), as plain values: non-rest 3 t_q (p0 + rho e.u + 3/2 rho
+// ((e.u)^2 - u^2/3)) resp. 3 t_q (Gamma mu + phi e.u + ...), the rest population taking
+// what mass (rho resp. phi) leaves.
+template <class L>
+__device__ double feq_fe_plane(int comp, int q, double rho, double phi, double ux, double uy, double uz, double A,
+                               double G) {
+    const double mu = A * (-phi + phi * phi * phi);
+    const double p0 = rho / 3.0 + A * (-0.5 * phi * phi + 0.75 * phi * phi * phi * phi);
+    const double usq = ux * ux + uy * uy + uz * uz;
+    double r = 0.0, sum = 0.0;
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+        const double eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
+        const double quad = 1.5 * (eu * eu - usq / 3.0);
+        const double v = comp == 0 ? 3.0 * L::w(i) * (p0 + eu * rho + quad * rho)
+                                   : 3.0 * L::w(i) * (G * mu + eu * phi + quad * phi);
+        sum += v;
+        if (i == q) r = v;
+    }
+    return q == 0 ? (comp == 0 ? rho : phi) - sum : r;
+}
+
 template <class L>
 __device__ __forceinline__ void canon_loc_rt(int layout, int q, const Geo &g, int &slot, uint32_t &node) {
 #pragma unroll
@@ -55,7 +78,12 @@ __global__ void k_init_plane(PlaneParams p) {
     if (n >= p.N) return;
     const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     const double ux = p.u[n], uy = p.u[p.N + n], uz = L::D == 3 ? p.u[2 * size_t(p.N) + n] : 0.0;
-    double h = heq_plane<L>(p.q, p.rho[n], ux, uy, uz, p.entropic);
+    double wq = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++)
+        if (i == p.q) wq = L::w(i);
+    double h = p.fe ? feq_fe_plane<L>(p.comp, p.q, p.rho[n], p.phi[n], ux, uy, uz, p.fe_a, p.fe_gamma) - wq
+                    : heq_plane<L>(p.q, p.rho[n], ux, uy, uz, p.entropic);
     if (p.df) h += p.df[n];
     int slot;
     uint32_t nd;
@@ -121,10 +149,10 @@ __global__ void k_macro(MacroParams p) {
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= p.N) return;
     const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
-    double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0};
+    double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0}, jf[3] = {0.0, 0.0, 0.0};
     const uint32_t fl = p.flags ? p.flags[n] : 0u;
     const bool vel = fl == 2u && p.ncomp == 1;
-    const bool half = fl == 3u && p.ncomp == 1;
+    const bool half = fl == 3u && (p.ncomp == 1 || p.model == M_FE);
     for (int c = 0; c < p.ncomp; c++) {
         const T *pop = static_cast<const T *>(p.pop) + size_t(c) * L::Q * p.S;
         C h[L::Q];
@@ -153,6 +181,11 @@ __global__ void k_macro(MacroParams p) {
                 dr += p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1 ? h[opp(i)] : h[i];
             rho[c] = double(C(1) + dr);
         }
+        if (c == 0) {
+            jf[0] = double(m.jx);
+            jf[1] = double(m.jy);
+            jf[2] = double(m.jz);
+        }
         j[0] += double(m.jx);
         j[1] += double(m.jy);
         j[2] += double(m.jz);
@@ -160,7 +193,14 @@ __global__ void k_macro(MacroParams p) {
     const double rt = rho[0] + rho[1];
     double v[3] = {0.0, 0.0, 0.0};
     const bool wall = fl == 1u;
-    if (vel) {
+    if (p.model == M_FE) {
+        // rho[1] is phi (the g lattice's zeroth moment); velocity (j + F/2)/rho of f alone
+        if (!wall) {
+            v[0] = (jf[0] + 0.5 * rho[0] * p.g[0]) / rho[0];
+            v[1] = (jf[1] + 0.5 * rho[0] * p.g[1]) / rho[0];
+            v[2] = L::D == 3 ? (jf[2] + 0.5 * rho[0] * p.g[2]) / rho[0] : 0.0;
+        }
+    } else if (vel) {
         for (int k = 0; k < 3; k++) v[k] = p.u_bc[k];
         if (L::D == 2) v[2] = 0.0;
     } else if (!wall) {
@@ -188,7 +228,8 @@ __global__ void k_macro(MacroParams p) {
     }
     if (p.bad) {
         bool ok = true;
-        for (int c = 0; c < p.ncomp; c++) ok = ok && (rho[c] > 0.0) && isfinite(rho[c]);
+        for (int c = 0; c < (p.model == M_FE ? 1 : p.ncomp); c++) ok = ok && (rho[c] > 0.0) && isfinite(rho[c]);
+        if (p.model == M_FE) ok = ok && isfinite(rho[1]);
         if (!ok) atomicAdd(p.bad, 1u);
     }
     if (p.fp64) {
@@ -206,21 +247,23 @@ constexpr int RED_BS = 256;
 constexpr int RED_K = 8;  // mass0, mass1, px, py, pz, ke, bad, (unused)
 
 // Per-block partial sums in a fixed order (grid-stride over nodes, tree in LDS).
+// phi2: the second density row is the free-energy order parameter phi (no mass, may be
+// negative), so momentum and the positivity check use rho alone
 __global__ __launch_bounds__(RED_BS) void k_diag_partials(const double *rho, const double *u, uint32_t N, int ncomp,
-                                                          double *partials) {
+                                                          int phi2, double *partials) {
     __shared__ double s[RED_K][RED_BS];
     double acc[RED_K] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t n = blockIdx.x * RED_BS + threadIdx.x; n < N; n += gridDim.x * RED_BS) {
         const double r0 = rho[n], r1 = ncomp == 2 ? rho[size_t(N) + n] : 0.0;
         const double ux = u[n], uy = u[size_t(N) + n], uz = u[2 * size_t(N) + n];
-        const double rt = r0 + r1;
+        const double rt = phi2 ? r0 : r0 + r1;
         acc[0] += r0;
         acc[1] += r1;
         acc[2] += rt * ux;
         acc[3] += rt * uy;
         acc[4] += rt * uz;
         acc[5] += ux * ux + uy * uy + uz * uz;
-        bool ok = (r0 > 0.0) && isfinite(r0) && (ncomp == 1 || ((r1 > 0.0) && isfinite(r1)));
+        bool ok = (r0 > 0.0) && isfinite(r0) && (ncomp == 1 || ((phi2 || r1 > 0.0) && isfinite(r1)));
         acc[6] += ok ? 0.0 : 1.0;
     }
     for (int k = 0; k < RED_K; k++) s[k][threadIdx.x] = acc[k];
@@ -267,9 +310,9 @@ hipError_t launch_macro(int lattice, int storage, const MacroParams &p, const La
     LBM_AUX_LAUNCH(k_macro, p);
 }
 
-hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, int ncomp, double *partials,
+hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, int ncomp, int phi2, double *partials,
                               int nblocks, double *out, hipStream_t s) {
-    k_diag_partials<<<nblocks, RED_BS, 0, s>>>(rho, u, N, ncomp, partials);
+    k_diag_partials<<<nblocks, RED_BS, 0, s>>>(rho, u, N, ncomp, phi2, partials);
     k_diag_final<<<1, 64, 0, s>>>(partials, nblocks, N, out);
     return hipGetLastError();
 }

@@ -58,6 +58,10 @@ hipError_t launch_step_bgk(int lattice, int storage, int sr, int layout, int fla
                            const LaunchCfg &c);
 hipError_t launch_step_mrt(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                            const LaunchCfg &c);
+// step_fe.hip: the free-energy order-parameter pre-pass (phi into p.psi) and step
+hipError_t launch_fe_phi(int lattice, int storage, int layout, bool flags, const StepParams &p, const LaunchCfg &c);
+hipError_t launch_step_fe(int lattice, int storage, int layout, bool flags, const StepParams &p,
+                          const LaunchCfg &c);
 // step_reg.hip, step_smag.hip
 hipError_t launch_step_reg(int lattice, int storage, int sr, int layout, int flags, const StepParams &p,
                            const LaunchCfg &c);
@@ -84,6 +88,9 @@ struct PlaneParams {
     const double *u;   // init: u[3][N]
     const double *df;  // init: optional perturbation plane [N]
     int entropic;      // init: entropic equilibrium instead of the polynomial one
+    int fe;            // init: free-energy equilibria (zero phi gradients) of lattice comp
+    const double *phi; // init, free energy: phi[N]
+    double fe_a, fe_gamma;
 };
 hipError_t launch_init_plane(int lattice, int storage, const PlaneParams &p, const LaunchCfg &c);
 hipError_t launch_get_plane(int lattice, int storage, const PlaneParams &p, const LaunchCfg &c);
@@ -109,7 +116,7 @@ struct MacroParams {
 hipError_t launch_macro(int lattice, int storage, const MacroParams &p, const LaunchCfg &c);
 
 // deterministic FP64 reduction of (rho[C][N], u[3][N]) into out[8]
-hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, int ncomp, double *partials,
+hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, int ncomp, int phi2, double *partials,
                               int nblocks, double *out, hipStream_t s);
 
 // MLP kernels (mlp.hip)

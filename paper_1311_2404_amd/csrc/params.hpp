@@ -5,7 +5,7 @@
 namespace lbm {
 
 enum Layout { LAYOUT_AB = 0, LAYOUT_AA_EVEN = 1, LAYOUT_AA_ODD = 2 };
-enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3, M_REG = 4, M_SMAG = 5 };
+enum Model { M_BGK = 0, M_MRT = 1, M_ELBM = 2, M_SC = 3, M_REG = 4, M_SMAG = 5, M_FE = 6 };
 
 constexpr int MLP_IN = 6;
 constexpr int MLP_H = 32;
@@ -33,6 +33,8 @@ struct StepParams {
     int has_force;
     double s[19];               // MRT rates in moment order
     double u_bc[3];             // velocity of the equilibrium velocity nodes (flag 2)
+    double tau_a, tau_b, tau_phi;  // free energy: f relaxation at phi = +1 / -1, g relaxation
+    double fe_a, fe_kappa, fe_gamma;  // free energy: A, kappa, Gamma
     double tau0;                // Smagorinsky: base relaxation time
     double smag_k;              // Smagorinsky: 4 cs^-4 C_S^2 = 36 C_S^2
     // entropic LBM

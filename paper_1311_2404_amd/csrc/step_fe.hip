@@ -11,9 +11,9 @@
 // tensor + rho u u).  grad and lap use the isotropic lattice-weight stencils on the phi
 // field of the pre-pass; a wall neighbour contributes the node's own phi (neutral
 // wetting).  f relaxes with tau_rho = tau_B + (phi + 1)/2 (tau_A - tau_B) and takes the
-// body force by the exact difference method around u = j/rho; g relaxes with tau_phi
-// towards its equilibrium at the velocity (j + F/2)/rho.  Stored values are plain
-// (unshifted) f and g.
+// body force by the exact difference method around u = j/rho (the difference of the
+// two equilibria written out); g relaxes with tau_phi
+// towards its equilibrium at the velocity (j + F/2)/rho.  Storage F64, F32 or shifted F32.
 #include "dispatch.hpp"
 #include "step.hpp"
 
@@ -33,12 +33,12 @@ __device__ __forceinline__ void fe_complete(C *v, const StepParams &p, const Geo
         if (p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1) v[i] = b[opp(i)];
 }
 
-// phi = sum_i g_i of the populations streaming into x (completed on half-way nodes)
+// phi = sum_i g_i of the populations streaming into x (completed on half-way nodes),
+// summed as 1 + sum_i (g_i - w_i)
 template <class L, class St, int LAYOUT, bool FLAGS>
-__global__ __launch_bounds__(256) void k_fe_phi(StepParams p) {
+__global__ __launch_bounds__(512) void k_fe_phi(StepParams p) {
     using T = typename St::T;
     using C = typename St::C;
-    static_assert(!St::shifted, "the free-energy kernels keep plain f and g");
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const int z = blockIdx.z;
@@ -51,17 +51,21 @@ __global__ __launch_bounds__(256) void k_fe_phi(StepParams p) {
     for (int i = 0; i < L::Q; i++) {
         int slot, dx, dy, dz;
         canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        v[i] = C(*pop_addr(gs, p.S, slot, g, dx, dy, dz));
+        v[i] = St::decode(*pop_addr(gs, p.S, slot, g, dx, dy, dz), C(L::w(i)));
     }
     if (FLAGS && p.flags[n] == 3) fe_complete<L, C>(v, p, g);
     C r = C(0);
 #pragma unroll
     for (int i = 0; i < L::Q; i++) r += v[i];
-    static_cast<C *>(const_cast<void *>(p.psi))[n] = r;
+    static_cast<C *>(const_cast<void *>(p.psi))[n] = C(1) + r;
 }
 
+// The step of both lattices, computed on the deviations h = f - w and k = g - w (the
+// paper's round-off minimising form): the f equilibria's deviations are
+// t_i (rho - 1) + 3 t_i (A(...) - kappa phi lap + rho e.u + ...) + gradient terms, so no
+// O(1) value is formed and a shifted storage keeps the small O(F) and O(u) parts.
 template <class L, class St, int LAYOUT, bool FLAGS>
-__global__ __launch_bounds__(256) void k_step_fe(StepParams p) {
+__global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
     using T = typename St::T;
     using C = typename St::C;
     constexpr int Q = L::Q;
@@ -74,40 +78,44 @@ __global__ __launch_bounds__(256) void k_step_fe(StepParams p) {
     const T *src = static_cast<const T *>(p.src);
     T *dst = static_cast<T *>(p.dst);
     const C *__restrict__ phis = static_cast<const C *>(p.psi);
-    C f[Q], gg[Q];
+    T rf[Q], rg[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         int slot, dx, dy, dz;
         canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        f[i] = C(LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i));
-        gg[i] = C(LBM_LOAD(pop_addr(src, S, Q + slot, g, dx, dy, dz), i));
+        rf[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
+        rg[i] = LBM_LOAD(pop_addr(src, S, Q + slot, g, dx, dy, dz), i);
     }
     const uint32_t fl = FLAGS ? p.flags[n] : 0u;
+    T of[Q], og[Q];
     if (fl == 1u) {
         // full-way bounce-back on both lattices
-        C t[Q];
-#pragma unroll
-        for (int i = 0; i < Q; i++) t[i] = f[opp(i)];
-#pragma unroll
-        for (int i = 0; i < Q; i++) f[i] = t[i];
-#pragma unroll
-        for (int i = 0; i < Q; i++) t[i] = gg[opp(i)];
-#pragma unroll
-        for (int i = 0; i < Q; i++) gg[i] = t[i];
-    } else {
-        if (FLAGS && fl == 3u) {
-            fe_complete<L, C>(f, p, g);
-            fe_complete<L, C>(gg, p, g);
-        }
-        C rho = C(0), phi = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            rho += f[i];
-            phi += gg[i];
-            jx += C(L::ex(i)) * f[i];
-            jy += C(L::ey(i)) * f[i];
-            jz += C(L::ez(i)) * f[i];
+            of[i] = rf[opp(i)];
+            og[i] = rg[opp(i)];
         }
+    } else {
+        C h[Q], k[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            h[i] = St::decode(rf[i], C(L::w(i)));
+            k[i] = St::decode(rg[i], C(L::w(i)));
+        }
+        if (FLAGS && fl == 3u) {
+            fe_complete<L, C>(h, p, g);
+            fe_complete<L, C>(k, p, g);
+        }
+        C drho = C(0), dphi = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            drho += h[i];
+            dphi += k[i];
+            jx += C(L::ex(i)) * h[i];
+            jy += C(L::ey(i)) * h[i];
+            jz += C(L::ez(i)) * h[i];
+        }
+        const C rho = C(1) + drho, phi = C(1) + dphi;
         // stencils on the pre-pass phi field
         const C p0x = phis[n];
         C gx = C(0), gy = C(0), gz = C(0), lap = C(0);
@@ -123,47 +131,54 @@ __global__ __launch_bounds__(256) void k_step_fe(StepParams p) {
         }
         const C A = C(p.fe_a), kap = C(p.fe_kappa);
         const C mu = A * (-phi + phi * phi * phi) - kap * lap;
-        const C pb = rho * C(1.0 / 3.0) + A * (C(-0.5) * phi * phi + C(0.75) * phi * phi * phi * phi);
-        const C iso = pb - kap * phi * lap;
+        // p0 - kappa phi lap without its rho/3 part (t_i rho - w_i = t_i (rho - 1) carries it)
+        const C iso = A * (C(-0.5) * phi * phi + C(0.75) * phi * phi * phi * phi) - kap * phi * lap;
         const C g2 = gx * gx + gy * gy + gz * gz;
         const C ax = C(p.g[0]), ay = C(p.g[1]), az = C(L::D == 3 ? p.g[2] : 0.0);
         const C irho = C(1) / rho;
         const C ux = jx * irho, uy = jy * irho, uz = jz * irho;
-        const C u1x = ux + ax, u1y = uy + ay, u1z = uz + az;
         const C vx = ux + C(0.5) * ax, vy = uy + C(0.5) * ay, vz = uz + C(0.5) * az;
-        const C usq = ux * ux + uy * uy + uz * uz, u1sq = u1x * u1x + u1y * u1y + u1z * u1z;
+        const C usq = ux * ux + uy * uy + uz * uz;
         const C vsq = vx * vx + vy * vy + vz * vz;
+        const C a2 = ax * (C(2) * ux + ax) + ay * (C(2) * uy + ay) + az * (C(2) * uz + az);
         const C itr = C(1) / (C(p.tau_b) + C(0.5) * (phi + C(1)) * (C(p.tau_a) - C(p.tau_b)));
         const C itp = C(1) / C(p.tau_phi);
         const C gmu = C(p.fe_gamma) * mu;
         C s0 = C(0), s1 = C(0), sg = C(0);
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            const C t3 = C(3 * L::w(i));
+            const C t = C(L::w(i)), t3 = C(3 * L::w(i));
             const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
-            const C eu1 = C(L::ex(i)) * u1x + C(L::ey(i)) * u1y + C(L::ez(i)) * u1z;
+            const C ea = C(L::ex(i)) * ax + C(L::ey(i)) * ay + C(L::ez(i)) * az;
             const C ev = C(L::ex(i)) * vx + C(L::ey(i)) * vy + C(L::ez(i)) * vz;
             const C eg = C(L::ex(i)) * gx + C(L::ey(i)) * gy + C(L::ez(i)) * gz;
-            const C grad_t = kap * C(L::w(i)) * (C(4.5) * eg * eg - C(3) * g2);
-            const C fe0 = t3 * (iso + eu * rho + C(1.5) * (eu * eu - usq * C(1.0 / 3.0)) * rho) + grad_t;
-            const C fe1 = t3 * (iso + eu1 * rho + C(1.5) * (eu1 * eu1 - u1sq * C(1.0 / 3.0)) * rho) + grad_t;
-            const C ge = t3 * (gmu + ev * phi + C(1.5) * (ev * ev - vsq * C(1.0 / 3.0)) * phi);
-            s0 += fe0;
-            s1 += fe1;
-            sg += ge;
-            f[i] = f[i] + (fe0 - f[i]) * itr + (fe1 - fe0);
-            gg[i] = gg[i] + (ge - gg[i]) * itp;
+            // deviations of the equilibria from w_i
+            const C hf = t * drho + t3 * (iso + eu * rho + C(1.5) * (eu * eu - usq * C(1.0 / 3.0)) * rho) +
+                         kap * t * (C(4.5) * eg * eg - C(3) * g2);
+            const C hg = t3 * (gmu + ev * phi + C(1.5) * (ev * ev - vsq * C(1.0 / 3.0)) * phi) - t;
+            // feq(u + a) - feq(u), written out (an O(F) term; no cancellation of O(1) values)
+            const C edm = t3 * rho * (ea + C(1.5) * (ea * (C(2) * eu + ea) - a2 * C(1.0 / 3.0)));
+            s0 += hf;
+            s1 += edm;
+            sg += hg;
+            h[i] = h[i] + (hf - h[i]) * itr + edm;
+            k[i] = k[i] + (hg - k[i]) * itp;
         }
-        const C fe0r = rho - s0, fe1r = rho - s1, ger = phi - sg;
-        f[0] = f[0] + (fe0r - f[0]) * itr + (fe1r - fe0r);
-        gg[0] = gg[0] + (ger - gg[0]) * itp;
+        // rest populations: what mass leaves (f_0 - w_0 = (rho - 1) - sum_i (f_i - w_i))
+        h[0] = h[0] + ((drho - s0) - h[0]) * itr - s1;
+        k[0] = k[0] + ((dphi - sg) - k[0]) * itp;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            of[i] = St::encode(h[i], C(L::w(i)), 0u);
+            og[i] = St::encode(k[i], C(L::w(i)), 0u);
+        }
     }
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         int slot, dx, dy, dz;
         post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), T(f[i]));
-        LBM_STORE(pop_addr(dst, S, Q + slot, g, dx, dy, dz), T(gg[i]));
+        LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), of[i]);
+        LBM_STORE(pop_addr(dst, S, Q + slot, g, dx, dy, dz), og[i]);
     }
 }
 
@@ -172,6 +187,7 @@ hipError_t with_fe_storage(int storage, F &&fn) {
     switch (storage) {
     case ST_F64: return fn(StF64{});
     case ST_F32: return fn(StF32{});
+    case ST_F32S: return fn(StF32S{});
     default: return hipErrorInvalidValue;
     }
 }

@@ -147,3 +147,32 @@ def test_velocity_nodes_arguments(lbm):
         assert ei.value.code == lbm.LBM_EINVAL
     finally:
         lbm.lbm_destroy(h)
+
+
+def test_free_energy_arguments(lbm):
+    h = lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_BGK, 4, 4, 4, 0.6)
+    try:
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_free_energy(h, 0.8, 1.0, 0.04, 0.04, 1.0)
+        assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    finally:
+        lbm.lbm_destroy(h)
+    h = lbm.lbm_create(lbm.LBM_D3Q19, lbm.LBM_FREE_ENERGY, 4, 4, 4, 0.6, (1e-6, 0, 0))
+    try:
+        lbm.lbm_set_free_energy(h, 0.8, 1.0, 0.04, 0.04, 1.0)
+        for bad in [(0.5, 1.0, 0.04, 0.04, 1.0), (0.8, 0.4, 0.04, 0.04, 1.0), (0.8, 1.0, float("nan"), 0.04, 1.0),
+                    (0.8, 1.0, 0.04, -1.0, 1.0), (0.8, 1.0, 0.04, 0.04, -1.0)]:
+            with pytest.raises(lbm.LbmError) as ei:
+                lbm.lbm_set_free_energy(h, *bad)
+            assert ei.value.code == lbm.LBM_EINVAL
+        for st, sr in [(lbm.LBM_BF16S, 0), (lbm.LBM_F16S, 0), (lbm.LBM_F16S, 1)]:
+            with pytest.raises(lbm.LbmError) as ei:
+                lbm.lbm_set_storage(h, st, lbm.LBM_AB, sr)
+            assert ei.value.code == lbm.LBM_EUNSUPPORTED
+        fl = np.zeros(64, np.uint8)
+        fl[:4] = lbm.LBM_VELOCITY
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_flags(h, fl)
+        assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    finally:
+        lbm.lbm_destroy(h)
