@@ -195,6 +195,45 @@ def run_extras(P, S, stream, torch):
                      "ke_after_220_steps": float(d[5]), "nonfinite_nodes": int(d[6])}
     out["d3q19_ldc_254_re1000_fp32"] = ldc
     print("[bench] cavity done", file=sys.stderr, flush=True)
+
+    # free-energy binary fluid: spinodal decomposition 254x100x100, the paper's binary
+    # benchmark (phi pre-pass + step of both lattices; algorithmic bytes per node: f and g
+    # read and written 2 x 2 x 19 x 4, the pre-pass's g read 19 x 4 and phi write 4, the
+    # step's phi read 4), and the binary Poiseuille flow of the validation section on its
+    # 64x256 grid run to the steady state, against the sharp-interface solution
+    import numpy as np
+    fe = {}
+    cs = S.spinodal()
+    for st, tag in [(P.LBM_F32S, "f32s"), (P.LBM_F32, "f32")]:
+        s = P.Sim.from_case(cs, st, P.LBM_AB, stream=stream)
+        s.step(20)
+        ms = _time_steps(s, stream, torch, 200)
+        d = s.diag()
+        s.close()
+        fe["spinodal_254x100x100_" + tag] = {"mlups": round(cs.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                                             "bytes_per_node": 388,
+                                             "hbm_gbs_algorithmic": round(388 * cs.n / (ms * 1e-3) / 1e9, 1),
+                                             "nonfinite_nodes": int(d[6])}
+    cp = S.binary_poiseuille()
+    s = P.Sim.from_case(cp, P.LBM_F32S, P.LBM_AB, stream=stream)
+    prev, steps = None, 0
+    while steps < 1000000:
+        s.step(50000)
+        steps += 50000
+        ux = s.macro()[1][0].reshape(cp.ny, cp.nx)[:, 0].copy()
+        if prev is not None and np.abs(ux - prev).max() < 1e-5 * np.abs(ux).max():
+            break
+        prev = ux
+    s.close()
+    yc, L, nu0, nu1, g = (cp.extra[k] for k in ("yc", "L", "nu0", "nu1", "g"))
+    yy = np.arange(cp.ny) - yc
+    ana = np.where(np.abs(yy) > L / 2, g / (2 * nu0) * (L ** 2 - yy ** 2),
+                   g * L ** 2 / 8 * (3 / nu0 + 1 / nu1 * (1 - 4 * yy ** 2 / L ** 2)))
+    fe["binary_poiseuille_64x256_f32s"] = {"steps": steps, "umax": float(ux.max()), "umax_analytic": float(ana.max()),
+                                           "vel_rel_l2_vs_analytic": float(np.linalg.norm(ux[1:-1] - ana[1:-1]) /
+                                                                           np.linalg.norm(ana[1:-1]))}
+    out["free_energy"] = fe
+    print("[bench] free energy done", file=sys.stderr, flush=True)
     return out
 
 
