@@ -201,7 +201,6 @@ def run_extras(P, S, stream, torch):
     # read and written 2 x 2 x 19 x 4, the pre-pass's g read 19 x 4 and phi write 4, the
     # step's phi read 4), and the binary Poiseuille flow of the validation section on its
     # 64x256 grid run to the steady state, against the sharp-interface solution
-    import numpy as np
     fe = {}
     cs = S.spinodal()
     for st, tag in [(P.LBM_F32S, "f32s"), (P.LBM_F32, "f32")]:
