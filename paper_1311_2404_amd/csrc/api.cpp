@@ -266,6 +266,7 @@ PlaneParams plane_params(const lbm_sim *s, int layout, int c, int q) {
     p.q = q;
     p.pop = s->buf[s->cur];
     p.plane = s->stage;
+    p.plain = s->model == LBM_FREE_ENERGY && c == 1;  // the free-energy g lattice is stored plain
     return p;
 }
 

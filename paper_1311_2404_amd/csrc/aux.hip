@@ -93,8 +93,8 @@ __global__ void k_init_plane(PlaneParams p) {
     for (int i = 0; i < L::Q; i++)
         if (i == p.q) w = L::w(i);
     T *pop = static_cast<T *>(p.pop) + size_t(p.comp) * L::Q * p.S;
-    // unshifted storages round f = w + h once; shifted ones round h
-    if constexpr (St::shifted) pop[size_t(slot) * p.S + nd] = St::encode(C(h), C(w), 0u);
+    // unshifted storages (and plain planes) round f = w + h once; shifted ones round h
+    if (St::shifted && !p.plain) pop[size_t(slot) * p.S + nd] = St::encode(C(h), C(w), 0u);
     else pop[size_t(slot) * p.S + nd] = T(w + h);
 }
 
@@ -114,7 +114,7 @@ __global__ void k_get_plane(PlaneParams p) {
         if (i == p.q) w = L::w(i);
     const T *pop = static_cast<const T *>(p.pop) + size_t(p.comp) * L::Q * p.S;
     const T v = pop[size_t(slot) * p.S + nd];
-    if constexpr (St::shifted) p.plane[n] = w + double(St::decode(v, C(w)));
+    if (St::shifted && !p.plain) p.plane[n] = w + double(St::decode(v, C(w)));
     else p.plane[n] = double(v);
 }
 
@@ -133,7 +133,7 @@ __global__ void k_set_plane(PlaneParams p) {
     for (int i = 0; i < L::Q; i++)
         if (i == p.q) w = L::w(i);
     T *pop = static_cast<T *>(p.pop) + size_t(p.comp) * L::Q * p.S;
-    if constexpr (St::shifted) pop[size_t(slot) * p.S + nd] = St::encode(C(p.plane[n] - w), C(w), 0u);
+    if (St::shifted && !p.plain) pop[size_t(slot) * p.S + nd] = St::encode(C(p.plane[n] - w), C(w), 0u);
     else pop[size_t(slot) * p.S + nd] = T(p.plane[n]);
 }
 
@@ -174,6 +174,28 @@ __global__ void k_macro(MacroParams p) {
         }
         const Macro<C> m = moments<L, C>(h);
         rho[c] = double(m.rho);
+        if (p.model == M_FE && c == 1) {
+            // the free-energy g lattice is stored plain: phi = sum_i g_i in FP64
+            double ph = 0.0, gv[L::Q];
+#pragma unroll
+            for (int i = 0; i < L::Q; i++) {
+                int slot;
+                uint32_t nd;
+                canon_loc<L>(p.layout, i, g, slot, nd);
+                gv[i] = double(pop[size_t(slot) * p.S + nd]);
+            }
+            if (half) {
+                double gb[L::Q];
+#pragma unroll
+                for (int i = 0; i < L::Q; i++) gb[i] = gv[i];
+#pragma unroll
+                for (int i = 0; i < L::Q; i++)
+                    if (p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1) gv[i] = gb[opp(i)];
+            }
+#pragma unroll
+            for (int i = 0; i < L::Q; i++) ph += gv[i];
+            rho[1] = ph;
+        }
         if (vel) {
             C dr = C(0);
 #pragma unroll

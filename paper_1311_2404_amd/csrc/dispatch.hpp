@@ -91,6 +91,8 @@ struct PlaneParams {
     int fe;            // init: free-energy equilibria (zero phi gradients) of lattice comp
     const double *phi; // init, free energy: phi[N]
     double fe_a, fe_gamma;
+    int plain;         // the stored values of this plane are plain f (the free-energy g
+                       // lattice in every storage), not f - w
 };
 hipError_t launch_init_plane(int lattice, int storage, const PlaneParams &p, const LaunchCfg &c);
 hipError_t launch_get_plane(int lattice, int storage, const PlaneParams &p, const LaunchCfg &c);

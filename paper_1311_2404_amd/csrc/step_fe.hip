@@ -13,7 +13,8 @@
 // wetting).  f relaxes with tau_rho = tau_B + (phi + 1)/2 (tau_A - tau_B) and takes the
 // body force by the exact difference method around u = j/rho (the difference of the
 // two equilibria written out); g relaxes with tau_phi
-// towards its equilibrium at the velocity (j + F/2)/rho.  Storage F64, F32 or shifted F32.
+// towards its equilibrium at the velocity (j + F/2)/rho.  Storage F64, F32 or shifted F32
+// for f; g is stored plain in all of them.
 #include "dispatch.hpp"
 #include "step.hpp"
 
@@ -33,8 +34,9 @@ __device__ __forceinline__ void fe_complete(C *v, const StepParams &p, const Geo
         if (p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1) v[i] = b[opp(i)];
 }
 
-// phi = sum_i g_i of the populations streaming into x (completed on half-way nodes),
-// summed as 1 + sum_i (g_i - w_i)
+// phi = sum_i g_i of the populations streaming into x (completed on half-way nodes); the
+// g lattice is stored plain in every storage (its equilibria are O(phi, mu), not centred
+// on w_i, so g - w_i would only lose digits)
 template <class L, class St, int LAYOUT, bool FLAGS>
 __global__ __launch_bounds__(512) void k_fe_phi(StepParams p) {
     using T = typename St::T;
@@ -51,19 +53,20 @@ __global__ __launch_bounds__(512) void k_fe_phi(StepParams p) {
     for (int i = 0; i < L::Q; i++) {
         int slot, dx, dy, dz;
         canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        v[i] = St::decode(*pop_addr(gs, p.S, slot, g, dx, dy, dz), C(L::w(i)));
+        v[i] = C(*pop_addr(gs, p.S, slot, g, dx, dy, dz));
     }
     if (FLAGS && p.flags[n] == 3) fe_complete<L, C>(v, p, g);
     C r = C(0);
 #pragma unroll
     for (int i = 0; i < L::Q; i++) r += v[i];
-    static_cast<C *>(const_cast<void *>(p.psi))[n] = C(1) + r;
+    static_cast<C *>(const_cast<void *>(p.psi))[n] = r;
 }
 
-// The step of both lattices, computed on the deviations h = f - w and k = g - w (the
-// paper's round-off minimising form): the f equilibria's deviations are
-// t_i (rho - 1) + 3 t_i (A(...) - kappa phi lap + rho e.u + ...) + gradient terms, so no
-// O(1) value is formed and a shifted storage keeps the small O(F) and O(u) parts.
+// The step of both lattices.  f is computed on its deviations h = f - w (the paper's
+// round-off minimising form): the f equilibria's deviations are t_i (rho - 1) + 3 t_i
+// (A(...) - kappa phi lap + rho e.u + ...) + gradient terms, so no O(1) value is formed
+// and a shifted storage keeps the small O(F) and O(u) parts.  g is computed and stored
+// plain (k = g): its values are O(phi, mu) themselves.
 template <class L, class St, int LAYOUT, bool FLAGS>
 __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
     using T = typename St::T;
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             h[i] = St::decode(rf[i], C(L::w(i)));
-            k[i] = St::decode(rg[i], C(L::w(i)));
+            k[i] = C(rg[i]);
         }
         if (FLAGS && fl == 3u) {
             fe_complete<L, C>(h, p, g);
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
             jy += C(L::ey(i)) * h[i];
             jz += C(L::ez(i)) * h[i];
         }
-        const C rho = C(1) + drho, phi = C(1) + dphi;
+        const C rho = C(1) + drho, phi = dphi;
         // stencils on the pre-pass phi field
         const C p0x = phis[n];
         C gx = C(0), gy = C(0), gz = C(0), lap = C(0);
@@ -155,7 +158,7 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
             // deviations of the equilibria from w_i
             const C hf = t * drho + t3 * (iso + eu * rho + C(1.5) * (eu * eu - usq * C(1.0 / 3.0)) * rho) +
                          kap * t * (C(4.5) * eg * eg - C(3) * g2);
-            const C hg = t3 * (gmu + ev * phi + C(1.5) * (ev * ev - vsq * C(1.0 / 3.0)) * phi) - t;
+            const C hg = t3 * (gmu + ev * phi + C(1.5) * (ev * ev - vsq * C(1.0 / 3.0)) * phi);
             // feq(u + a) - feq(u), written out (an O(F) term; no cancellation of O(1) values)
             const C edm = t3 * rho * (ea + C(1.5) * (ea * (C(2) * eu + ea) - a2 * C(1.0 / 3.0)));
             s0 += hf;
@@ -164,13 +167,14 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
             h[i] = h[i] + (hf - h[i]) * itr + edm;
             k[i] = k[i] + (hg - k[i]) * itp;
         }
-        // rest populations: what mass leaves (f_0 - w_0 = (rho - 1) - sum_i (f_i - w_i))
+        // rest populations: what mass leaves (f_0 - w_0 = (rho - 1) - sum_i (f_i - w_i),
+        // g_0 = phi - sum_i g_i)
         h[0] = h[0] + ((drho - s0) - h[0]) * itr - s1;
-        k[0] = k[0] + ((dphi - sg) - k[0]) * itp;
+        k[0] = k[0] + ((phi - sg) - k[0]) * itp;
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             of[i] = St::encode(h[i], C(L::w(i)), 0u);
-            og[i] = St::encode(k[i], C(L::w(i)), 0u);
+            og[i] = T(k[i]);
         }
     }
 #pragma unroll
