@@ -61,6 +61,23 @@ def stored_traffic(kernel_tag, per_launch_nodes):
     return rec.get("hbm_bytes_per_launch")
 
 
+# VALU issue slots of the chip: 256 CUs x 4 SIMDs at 2.4 GHz, in SIMD-cycles per second.
+# A full-rate wave64 instruction holds a 16-lane SIMD for 4 cycles, a transcendental for 16.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9
+
+
+def stored_valu(kernel_tag, tu):
+    """SIMD-cycles per node of an ALU-bound step from committed rocprofv3 VALU counter
+    summaries, only if they were taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "valu_%s.json" % kernel_tag)
+    if not os.path.exists(p):
+        return None
+    rec = json.load(open(p))
+    if rec.get("source_hash") != kernel_source_hash(tu):
+        return None
+    return rec
+
+
 def bytes_per_node(storage):
     from paper_1311_2404_amd import ELEM_BYTES
     return 2 * 19 * ELEM_BYTES[storage]
@@ -74,6 +91,26 @@ def _time_steps(sim, stream, torch, steps):
     e1.record(stream)
     sim.sync()
     return e0.elapsed_time(e1) / steps
+
+
+def entropic_profile(P, S, stream, torch, steps, warmup):
+    """The entropic step alone, for kernel traces and counter passes: the 256^3 vortex in
+    FP32 storage, AB, Newton from the series first guess.  `warmup` steps run with the
+    Newton statistics on; then `steps` steps are timed without them."""
+    c4 = S.c4_elbm_taylor_green(n=256)
+    s = P.Sim.from_case(c4, P.LBM_F32, P.LBM_AB, stream=stream)
+    P.lbm_set_elbm(s.h, 1, 1e-10, 20)
+    P.lbm_elbm_stats(s.h, enable=True, reset=True)
+    s.step(warmup)
+    hist, nonconv = P.lbm_elbm_stats(s.h, enable=False)
+    ms = _time_steps(s, stream, torch, steps)
+    s.close()
+    k = np.arange(len(hist))
+    return {"workload": "D3Q19 entropic LBM 256^3 vortex, u0=0.05, nu=1e-5, FP32 storage, AB, "
+                        "Newton from the series guess", "nodes": c4.n, "warmup": warmup, "steps": steps,
+            "mlups": round(c4.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+            "warmup_mean_newton_iters": round(float((k * hist).sum() / max(hist.sum(), 1)), 4),
+            "warmup_nonconverged": int(nonconv)}
 
 
 def run_extras(P, S, stream, torch):
@@ -91,7 +128,10 @@ def run_extras(P, S, stream, torch):
         s.step(c3.steps)
         us[(st, sr)] = s.macro()[1]
         s.close()
-        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")] = {"mlups": round(c3.n / ms / 1e3, 1)}
+        b = bytes_per_node(st) + 1  # populations read and written, plus the flag byte
+        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")] = {
+            "mlups": round(c3.n / ms / 1e3, 1), "bytes_per_node": b,
+            "hbm_gbs_algorithmic": round(b * c3.n / (ms * 1e-3) / 1e9, 1)}
     ref = us[(P.LBM_F64, 0)]
     for (st, sr), u in us.items():
         rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")]["vel_rel_l2_vs_fp64"] = float(
@@ -140,6 +180,15 @@ def run_extras(P, S, stream, torch):
                       "mean_newton_iters": round(float((k * hist).sum() / max(hist.sum(), 1)), 4),
                       "nonconverged": int(nonconv),
                       "vel_rel_l2_vs_newton_from_2": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))}
+        rec = stored_valu("d3q19_elbm_f32_ab_256", "step_elbm.hip") if init == 1 else None
+        if rec:
+            # VALU-issue roofline from the counted SIMD-cycles per node (series guess)
+            ach = rec["simd_cycles_per_node"] * c4.n / (ms * 1e-3)
+            elbm[name]["roofline"] = {"bound": "alu", "achieved": round(ach / 1e12, 4),
+                                      "peak": round(VALU_ISSUE_PEAK / 1e12, 4),
+                                      "unit": "T SIMD-cycles/s (VALU issue)",
+                                      "frac": round(ach / VALU_ISSUE_PEAK, 4),
+                                      "simd_cycles_per_node": rec["simd_cycles_per_node"]}
     s.close()
     out["d3q19_elbm_taylor_green_256_fp32"] = elbm
     print("[bench] ELBM done", file=sys.stderr, flush=True)
@@ -294,6 +343,8 @@ def main():
                     help="also run 3 plain device copies of MIB MiB (calibrates HBM byte counters in profiles)")
     ap.add_argument("--precision-sweep", action="store_true",
                     help="run only the D2Q9 Taylor-Green precision study over u0 and storages (JSON line)")
+    ap.add_argument("--entropic-profile", action="store_true",
+                    help="run only the entropic 256^3 step (series guess), for traces and counters (JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -314,6 +365,9 @@ def main():
         res = precision_sweep(P, S, stream)
         print(json.dumps({"precision_sweep": res, "lattice": "D2Q9 256^2", "re": 1000,
                           "wall_s": round(time.perf_counter() - t0, 1)}))
+        return
+    if args.entropic_profile:
+        print(json.dumps(entropic_profile(P, S, stream, torch, args.steps, args.warmup)))
         return
     layout = P.LBM_AA if args.layout == "aa" else P.LBM_AB
     n = args.n

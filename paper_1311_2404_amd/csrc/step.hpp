@@ -446,7 +446,7 @@ __global__ __launch_bounds__(512) void k_psi(StepParams p) {
         for (int i = 0; i < L::Q; i++) {
             int slot, dx, dy, dz;
             canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            r += St::decode(*pop_addr(fc, p.S, slot, g, dx, dy, dz), C(L::w(i)));
+            r += St::decode(LBM_LOAD(pop_addr(fc, p.S, slot, g, dx, dy, dz), i), C(L::w(i)));
         }
         const C rho = C(1) + r;
         psi[size_t(c) * p.N + n] = p.psi_mode == 1 ? C(1) - exp(-rho) : rho;

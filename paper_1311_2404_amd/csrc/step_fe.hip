@@ -53,7 +53,7 @@ __global__ __launch_bounds__(512) void k_fe_phi(StepParams p) {
     for (int i = 0; i < L::Q; i++) {
         int slot, dx, dy, dz;
         canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        v[i] = C(*pop_addr(gs, p.S, slot, g, dx, dy, dz));
+        v[i] = C(LBM_LOAD(pop_addr(gs, p.S, slot, g, dx, dy, dz), i));
     }
     if (FLAGS && p.flags[n] == 3) fe_complete<L, C>(v, p, g);
     C r = C(0);
