@@ -58,6 +58,20 @@ __device__ __forceinline__ T pop_load(const T *ptr, int i) {
 #else
 #define LBM_STORE(ptr, v) __builtin_nontemporal_store((v), (ptr))
 #endif
+// Stores of population i.  The AA odd step writes x-moving populations one element off
+// the wave's 256-byte segment, so each wave leaves a partly written 64-byte sector at
+// both ends that the neighbouring wave completes.  Those stores go without the hint: the
+// line then waits in L2 for its other half instead of reaching HBM as a partial write.
+template <class L, int LAYOUT, class T>
+__device__ __forceinline__ void pop_store(T *ptr, T v, int i) {
+#if defined(LBM_PLAIN_STORES)
+    *ptr = v;
+#else
+    if (LAYOUT == lbm::LAYOUT_AA_ODD && L::ex(i) != 0) *ptr = v;
+    else __builtin_nontemporal_store(v, ptr);
+#endif
+}
+#define LBM_STORE_POP(ptr, v, i) pop_store<L, LAYOUT>((ptr), (v), (i))
 
 namespace lbm {
 
@@ -323,7 +337,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
             if constexpr (LAYOUT == LAYOUT_AB) LBM_STORE(pop_addr(dst, S, slot, gs, 0, 0, 0), out[i]);
-            else LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), out[i]);
+            else LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), out[i], i);
         }
     }
     if constexpr (ELBM) {
@@ -414,7 +428,7 @@ __global__ __launch_bounds__(512) void k_step_elbm_mlp(StepParams p) {
         for (int i = 0; i < Q; i++) {
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), out[i]);
+            LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), out[i], i);
         }
     }
     if (p.stats) {
@@ -532,7 +546,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
             if constexpr (sizeof(T) == 2) rnd = hash32(((n * 19u + uint32_t(i)) * 2u + uint32_t(c)) ^ key);
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            LBM_STORE(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), rnd));
+            LBM_STORE_POP(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), rnd), i);
         }
     }
 }

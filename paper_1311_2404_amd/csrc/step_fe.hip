@@ -181,8 +181,8 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
     for (int i = 0; i < Q; i++) {
         int slot, dx, dy, dz;
         post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        LBM_STORE(pop_addr(dst, S, slot, g, dx, dy, dz), of[i]);
-        LBM_STORE(pop_addr(dst, S, Q + slot, g, dx, dy, dz), og[i]);
+        LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), of[i], i);
+        LBM_STORE_POP(pop_addr(dst, S, Q + slot, g, dx, dy, dz), og[i], i);
     }
 }
 
