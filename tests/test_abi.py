@@ -47,13 +47,23 @@ def test_library_exports_every_declared_symbol(lbm):
     ((0, 0, 8, 8, 2, 0.8), -1),      # D2Q9 with nz > 1
     ((1, 0, 8, 8, 8, 0.5), -1),      # tau must exceed 1/2
     ((1, 0, 8, 8, 8, float("nan")), -1),
-    ((1, 0, 70000, 70000, 1000, 0.8), -1),  # N >= 2^32
+    ((1, 0, 70000, 70000, 1000, 0.8), -1),  # ny > 65535 and N >= 2^32
+    ((1, 0, 8, 65536, 8, 0.8), -1),         # ny > 65535 (grid y limit)
+    ((1, 0, 8, 8, 65536, 0.8), -1),         # nz > 65535 (grid z limit)
+    ((1, 0, 65536, 65535, 2, 0.8), -1),     # N = 2^33 - 2^17 >= 2^32 with ny, nz in range
+    ((1, 0, 65536, 256, 256, 0.8), -1),     # N = 2^32 exactly
 ])
 def test_create_rejects_bad_arguments(lbm, args, code):
     with pytest.raises(lbm.LbmError) as ei:
         lbm.lbm_create(*args)
     assert ei.value.code == code
     assert lbm.lbm_last_error(None)
+
+
+def test_create_accepts_the_largest_grid(lbm):
+    # N = 2^32 - 2^24 nodes, every axis within its limit; create allocates nothing
+    h = lbm.lbm_create(1, 0, 65536, 256, 255, 0.8)
+    lbm.lbm_destroy(h)
 
 
 def test_elbm_rejects_force_and_state_errors(lbm):
