@@ -139,6 +139,26 @@ def run_extras(P, S, stream, torch):
     out["d3q19_mrt_duct_128x128x512_5000_steps"] = rows
     print("[bench] MRT duct done", file=sys.stderr, flush=True)
 
+    # Diagnostics (kinetic energy, mass, momentum) on the 256^3 Taylor-Green state: one call
+    # is the macroscopic pass (populations in, FP64 rho and u out), the two-stage FP64
+    # reduction over those fields and the copy of the 8 sums to the host
+    c2 = S.c2_taylor_green(n=256)
+    diag = {}
+    for st in (P.LBM_F32, P.LBM_F32S, P.LBM_BF16S):
+        s = P.Sim.from_case(c2, st, P.LBM_AB, stream=stream)
+        s.diag()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            s.diag()
+        ms = (time.perf_counter() - t0) / 20 * 1e3
+        s.close()
+        b = bytes_per_node(st) // 2 + 4 * 8 + 4 * 8  # populations read, FP64 rho and u written, read back
+        diag[P.STORAGE_NAMES[st]] = {"ms_per_call": round(ms, 4), "bytes_per_node": b,
+                                     "hbm_gbs_algorithmic": round(b * c2.n / (ms * 1e-3) / 1e9, 1)}
+    out["d3q19_diagnostics_256"] = diag
+    del c2
+    print("[bench] diagnostics done", file=sys.stderr, flush=True)
+
     # D3Q19 entropic LBM 256^3: Newton from alpha = 2 vs from the trained MLP proposal
     c4 = S.c4_elbm_taylor_green(n=256)
     s = P.Sim.from_case(c4, P.LBM_F32, P.LBM_AB, stream=stream)

@@ -142,19 +142,53 @@ __global__ void k_set_plane(PlaneParams p) {
 // Equilibrium velocity nodes report the density of their completed population set (the
 // populations streamed from walls replaced by their opposites) and the prescribed velocity;
 // half-way bounce-back nodes report the moments of their completed set.
-template <class L, class St>
-__global__ void k_macro(MacroParams p) {
+//
+// One instantiation per model kind (one component, Shan-Chen, free energy) and per presence
+// of node flags, each holding only what it uses.  A single kernel for every model kept two
+// components' populations, the free-energy sums and per-component arrays under runtime
+// indices live at once and spilled (D3Q19: 208 B/lane with FP32 storage, 1 104 with
+// shifted FP32), which made the output and the diagnostics built on it 4-5x slower.
+enum { MK_ONE = 0, MK_SC = 1, MK_FE = 2 };
+
+template <class L, class St, int KIND, bool FL>
+__global__ __launch_bounds__(256) void k_macro(MacroParams p) {
     using T = typename St::T;
     using C = typename St::C;
+    constexpr int NC = KIND == MK_ONE ? 1 : 2;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= p.N) return;
     const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0}, jf[3] = {0.0, 0.0, 0.0};
-    const uint32_t fl = p.flags ? p.flags[n] : 0u;
-    const bool vel = fl == 2u && p.ncomp == 1;
-    const bool half = fl == 3u && (p.ncomp == 1 || p.model == M_FE);
-    for (int c = 0; c < p.ncomp; c++) {
+    const uint32_t fl = FL ? p.flags[n] : 0u;
+    const bool vel = FL && KIND == MK_ONE && fl == 2u;
+    const bool half = FL && KIND != MK_SC && fl == 3u;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
         const T *pop = static_cast<const T *>(p.pop) + size_t(c) * L::Q * p.S;
+        if (KIND == MK_FE && c == 1) {
+            // the free-energy g lattice is stored plain: phi = sum_i g_i in FP64
+            double gv[L::Q];
+#pragma unroll
+            for (int i = 0; i < L::Q; i++) {
+                int slot;
+                uint32_t nd;
+                canon_loc<L>(p.layout, i, g, slot, nd);
+                gv[i] = double(pop[size_t(slot) * p.S + nd]);
+            }
+            if (half) {
+                double gb[L::Q];
+#pragma unroll
+                for (int i = 0; i < L::Q; i++) gb[i] = gv[i];
+#pragma unroll
+                for (int i = 0; i < L::Q; i++)
+                    if (p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1) gv[i] = gb[opp(i)];
+            }
+            double ph = 0.0;
+#pragma unroll
+            for (int i = 0; i < L::Q; i++) ph += gv[i];
+            rho[1] = ph;
+            continue;
+        }
         C h[L::Q];
 #pragma unroll
         for (int i = 0; i < L::Q; i++) {
@@ -174,28 +208,6 @@ __global__ void k_macro(MacroParams p) {
         }
         const Macro<C> m = moments<L, C>(h);
         rho[c] = double(m.rho);
-        if (p.model == M_FE && c == 1) {
-            // the free-energy g lattice is stored plain: phi = sum_i g_i in FP64
-            double ph = 0.0, gv[L::Q];
-#pragma unroll
-            for (int i = 0; i < L::Q; i++) {
-                int slot;
-                uint32_t nd;
-                canon_loc<L>(p.layout, i, g, slot, nd);
-                gv[i] = double(pop[size_t(slot) * p.S + nd]);
-            }
-            if (half) {
-                double gb[L::Q];
-#pragma unroll
-                for (int i = 0; i < L::Q; i++) gb[i] = gv[i];
-#pragma unroll
-                for (int i = 0; i < L::Q; i++)
-                    if (p.flags[g.at(-L::ex(i), -L::ey(i), -L::ez(i))] == 1) gv[i] = gb[opp(i)];
-            }
-#pragma unroll
-            for (int i = 0; i < L::Q; i++) ph += gv[i];
-            rho[1] = ph;
-        }
         if (vel) {
             C dr = C(0);
 #pragma unroll
@@ -212,10 +224,9 @@ __global__ void k_macro(MacroParams p) {
         j[1] += double(m.jy);
         j[2] += double(m.jz);
     }
-    const double rt = rho[0] + rho[1];
     double v[3] = {0.0, 0.0, 0.0};
     const bool wall = fl == 1u;
-    if (p.model == M_FE) {
+    if (KIND == MK_FE) {
         // rho[1] is phi (the g lattice's zeroth moment); velocity (j + F/2)/rho of f alone
         if (!wall) {
             v[0] = (jf[0] + 0.5 * rho[0] * p.g[0]) / rho[0];
@@ -226,9 +237,11 @@ __global__ void k_macro(MacroParams p) {
         for (int k = 0; k < 3; k++) v[k] = p.u_bc[k];
         if (L::D == 2) v[2] = 0.0;
     } else if (!wall) {
-        if (p.model == M_SC) {
+        if (KIND == MK_SC) {
+            const double rt = rho[0] + rho[1];
             const C *psi = static_cast<const C *>(p.psi);
             double F[3] = {0.0, 0.0, 0.0};
+#pragma unroll
             for (int c = 0; c < 2; c++) {
                 const C *po = psi + size_t(1 - c) * p.N;
                 double s[3] = {0.0, 0.0, 0.0};
@@ -249,18 +262,20 @@ __global__ void k_macro(MacroParams p) {
         }
     }
     if (p.bad) {
-        bool ok = true;
-        for (int c = 0; c < (p.model == M_FE ? 1 : p.ncomp); c++) ok = ok && (rho[c] > 0.0) && isfinite(rho[c]);
-        if (p.model == M_FE) ok = ok && isfinite(rho[1]);
+        bool ok = (rho[0] > 0.0) && isfinite(rho[0]);
+        if (KIND == MK_SC) ok = ok && (rho[1] > 0.0) && isfinite(rho[1]);
+        if (KIND == MK_FE) ok = ok && isfinite(rho[1]);
         if (!ok) atomicAdd(p.bad, 1u);
     }
     if (p.fp64) {
         double *ro = static_cast<double *>(p.rho_out), *uo = static_cast<double *>(p.u_out);
-        for (int c = 0; c < p.ncomp; c++) ro[size_t(c) * p.N + n] = rho[c];
+#pragma unroll
+        for (int c = 0; c < NC; c++) ro[size_t(c) * p.N + n] = rho[c];
         for (int k = 0; k < 3; k++) uo[size_t(k) * p.N + n] = v[k];
     } else {
         float *ro = static_cast<float *>(p.rho_out), *uo = static_cast<float *>(p.u_out);
-        for (int c = 0; c < p.ncomp; c++) ro[size_t(c) * p.N + n] = float(rho[c]);
+#pragma unroll
+        for (int c = 0; c < NC; c++) ro[size_t(c) * p.N + n] = float(rho[c]);
         for (int k = 0; k < 3; k++) uo[size_t(k) * p.N + n] = float(v[k]);
     }
 }
@@ -329,7 +344,25 @@ hipError_t launch_set_plane(int lattice, int storage, const PlaneParams &p, cons
     LBM_AUX_LAUNCH(k_set_plane, p);
 }
 hipError_t launch_macro(int lattice, int storage, const MacroParams &p, const LaunchCfg &c) {
-    LBM_AUX_LAUNCH(k_macro, p);
+    return with_lattice(lattice, [&](auto lt) {
+        using L = decltype(lt);
+        return with_storage<false>(storage, 0, [&](auto st) {
+            using St = decltype(st);
+            const dim3 grid = flat_grid(p.N, 256);
+            const bool fl = p.flags != nullptr;
+            if (p.model == M_SC) {
+                if (fl) k_macro<L, St, MK_SC, true><<<grid, 256, 0, c.stream>>>(p);
+                else k_macro<L, St, MK_SC, false><<<grid, 256, 0, c.stream>>>(p);
+            } else if (p.model == M_FE) {
+                if (fl) k_macro<L, St, MK_FE, true><<<grid, 256, 0, c.stream>>>(p);
+                else k_macro<L, St, MK_FE, false><<<grid, 256, 0, c.stream>>>(p);
+            } else {
+                if (fl) k_macro<L, St, MK_ONE, true><<<grid, 256, 0, c.stream>>>(p);
+                else k_macro<L, St, MK_ONE, false><<<grid, 256, 0, c.stream>>>(p);
+            }
+            return hipGetLastError();
+        });
+    });
 }
 
 hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, int ncomp, int phi2, double *partials,
