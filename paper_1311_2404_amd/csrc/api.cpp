@@ -615,7 +615,7 @@ int lbm_diag(lbm_sim *s, double out[8]) {
     if (!s->ready) return fail(s, LBM_ESTATE, "no state yet: call lbm_init_eq or lbm_set_f");
     int rc = ensure_macro_scratch(s);
     if (rc) return rc;
-    const int nblocks = 512;
+    const int nblocks = 2048;  // 8 workgroups per CU for the partial sums
     if (!s->red_d) HIPCHK(s, hipMalloc(&s->red_d, sizeof(double) * (size_t(nblocks) * 8 + 8)));
     double *rd = s->macro_d, *ud = s->macro_d + size_t(s->C) * s->N;
     rc = macro_into(s, rd, ud, 1, nullptr);

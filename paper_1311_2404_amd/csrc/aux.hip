@@ -313,13 +313,23 @@ __global__ __launch_bounds__(RED_BS) void k_diag_partials(const double *rho, con
     if (threadIdx.x < RED_K) partials[size_t(blockIdx.x) * RED_K + threadIdx.x] = s[threadIdx.x][0];
 }
 
-__global__ void k_diag_final(const double *partials, int nblocks, uint32_t N, double *out) {
-    const int k = threadIdx.x;
-    if (k >= RED_K) return;
-    double acc = 0.0;
-    for (int b = 0; b < nblocks; b++) acc += partials[size_t(b) * RED_K + k];
-    if (k == 5) acc *= 0.5 / double(N);
-    out[k] = acc;
+// The block partials summed in a fixed order: each thread takes a fixed stride of blocks,
+// then a tree in LDS.  (One thread per sum walking every block was a chain of dependent
+// loads: 79 us for 512 blocks.)
+__global__ __launch_bounds__(RED_BS) void k_diag_final(const double *partials, int nblocks, uint32_t N,
+                                                       double *out) {
+    __shared__ double s[RED_K][RED_BS];
+    double acc[RED_K] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += RED_BS)
+        for (int k = 0; k < RED_K; k++) acc[k] += partials[size_t(b) * RED_K + k];
+    for (int k = 0; k < RED_K; k++) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = RED_BS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < RED_K; k++) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < RED_K) out[threadIdx.x] = threadIdx.x == 5 ? s[5][0] * (0.5 / double(N)) : s[threadIdx.x][0];
 }
 
 }  // namespace
@@ -368,7 +378,7 @@ hipError_t launch_macro(int lattice, int storage, const MacroParams &p, const La
 hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, int ncomp, int phi2, double *partials,
                               int nblocks, double *out, hipStream_t s) {
     k_diag_partials<<<nblocks, RED_BS, 0, s>>>(rho, u, N, ncomp, phi2, partials);
-    k_diag_final<<<1, 64, 0, s>>>(partials, nblocks, N, out);
+    k_diag_final<<<1, RED_BS, 0, s>>>(partials, nblocks, N, out);
     return hipGetLastError();
 }
 

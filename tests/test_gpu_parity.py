@@ -279,6 +279,34 @@ def test_set_get_roundtrip_all_storages():
             s.close()
 
 
+@pytest.mark.parametrize("kind", ["bgk", "bgk_walls", "shan_chen", "free_energy"])
+@pytest.mark.parametrize("storage", ["F64", "F32S"])
+def test_diag_sums_match_the_macroscopic_fields(kind, storage):
+    """The diagnostics' FP64 block reduction against the same sums taken on the host from
+    the macroscopic fields of the same state (a ragged 67x23x11 grid, 10 steps in)."""
+    from test_gpu_free_energy import fe_random
+    shape = (67, 23, 11)
+    if kind == "free_energy":
+        c = fe_random(S.D3Q19, *shape)
+    elif kind == "shan_chen":
+        c = random_case(S.D3Q19, S.SHANCHEN, *shape, tau=0.9, G=0.9, psi=0, du=0.02, drho=0.05)
+    else:
+        c = random_case(S.D3Q19, S.BGK, *shape, tau=0.7, force=(1e-5, 0, -2e-5), walls=kind == "bgk_walls")
+    s = P.Sim.from_case(c, getattr(P, "LBM_" + storage))
+    s.step(10)
+    rho, u = s.macro()
+    d = s.diag()
+    s.close()
+    n = c.nx * c.ny * c.nz
+    # momentum uses the mixture density for Shan-Chen and rho alone for the free-energy model
+    rt = rho[0] + rho[1] if kind == "shan_chen" else rho[0]
+    want = [rho[0].sum(), rho[1].sum() if rho.shape[0] == 2 else 0.0,
+            (rt * u[0]).sum(), (rt * u[1]).sum(), (rt * u[2]).sum(), 0.5 * (u * u).sum() / n, 0.0]
+    for k in range(7):
+        scale = max(abs(want[k]), 1e-300) if k in (0, 1, 5) else max(rt.sum() * np.abs(u).max(), 1e-300)
+        assert abs(d[k] - want[k]) <= 1e-12 * scale, (kind, storage, k, d[k], want[k])
+
+
 def test_diag_conservation_and_divergence_flag():
     c = random_case(S.D3Q19, S.BGK, 24, 10, 8, walls=True)
     s = P.Sim.from_case(c, P.LBM_F64)
