@@ -221,13 +221,26 @@ __global__ __launch_bounds__(TB) void k_mlp_grad(const float *w, const float *xa
     if (lane == 0) part[MLP_NPARAM] = e2;
 }
 
-__global__ void k_mlp_reduce(const float *partials, int nparts, float *grad, double *loss_acc, int64_t nbatch) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > MLP_NPARAM) return;
+// The block partials summed per parameter (and the loss) in FP64, in a fixed order: four
+// threads per parameter each take every fourth block, and their sums are added in LDS.
+// (One thread per parameter walking every block kept only 6 workgroups busy: 16.6 us per
+// 4096-row minibatch.)
+constexpr int RED_SPLIT = 4;  // the LDS sum below is written out for four parts
+__global__ __launch_bounds__(64 * RED_SPLIT) void k_mlp_reduce(const float *partials, int nparts, float *grad,
+                                                               double *loss_acc, int64_t nbatch) {
+    __shared__ double s[RED_SPLIT][64];
+    const int j = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + j;
     double acc = 0.0;
-    for (int b = 0; b < nparts; b++) acc += double(partials[size_t(b) * (MLP_NPARAM + 1) + k]);
-    if (k < MLP_NPARAM) grad[k] = float(acc);
-    else if (loss_acc) *loss_acc += acc / double(nbatch);
+    if (k <= MLP_NPARAM)
+        for (int b = part; b < nparts; b += RED_SPLIT) acc += double(partials[size_t(b) * (MLP_NPARAM + 1) + k]);
+    s[part][j] = acc;
+    __syncthreads();
+    if (part == 0 && k <= MLP_NPARAM) {
+        const double tot = (s[0][j] + s[1][j]) + (s[2][j] + s[3][j]);
+        if (k < MLP_NPARAM) grad[k] = float(tot);
+        else if (loss_acc) *loss_acc += tot / double(nbatch);
+    }
 }
 
 __global__ void k_adam(float *w, const float *g, float *m, float *v, float b1t, float b2t, float lr) {
@@ -366,7 +379,7 @@ hipError_t mlp_loss_grad(const float *w, const float *x, const double *t, int64_
     if (n <= 0 || nparts < int((n + TB - 1) / TB)) return hipErrorInvalidValue;
     const int nb = int((n + TB - 1) / TB);
     k_mlp_grad<<<nb, TB, 0, s>>>(w, x, t, 0, n, n, 0, 0, mu, isd, 0.0, 1.0, partials);
-    k_mlp_reduce<<<(MLP_NPARAM + 1 + 255) / 256, 256, 0, s>>>(partials, nb, grad, loss, n);
+    k_mlp_reduce<<<(MLP_NPARAM + 1 + 63) / 64, 64 * RED_SPLIT, 0, s>>>(partials, nb, grad, loss, n);
     return hipGetLastError();
 }
 
@@ -402,7 +415,7 @@ hipError_t mlp_train_batch(const float *w, const float *x, const double *t, int6
                            double tinv, float *partials, float *grad, double *loss_acc, hipStream_t s) {
     const int nb = int((nbatch + TB - 1) / TB);
     k_mlp_grad<<<nb, TB, 0, s>>>(w, x, t, row0, nbatch, n_all, pa, pb, mu, isd, tmean, tinv, partials);
-    k_mlp_reduce<<<(MLP_NPARAM + 1 + 255) / 256, 256, 0, s>>>(partials, nb, grad, loss_acc, nbatch);
+    k_mlp_reduce<<<(MLP_NPARAM + 1 + 63) / 64, 64 * RED_SPLIT, 0, s>>>(partials, nb, grad, loss_acc, nbatch);
     return hipGetLastError();
 }
 
