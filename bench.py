@@ -395,12 +395,12 @@ def main():
     case = S.c2_taylor_green(n=n, steps=ERR_STEPS)
     print("[bench] inputs ready: D3Q19 BGK TGV %d^3" % n, file=sys.stderr, flush=True)
 
-    def make(storage):
-        s = P.Sim.from_case(case, storage, layout, stream=stream)
+    def make(storage, lay=None):
+        s = P.Sim.from_case(case, storage, layout if lay is None else lay, stream=stream)
         return s
 
-    def timed(storage, steps, warmup):
-        s = make(storage)
+    def timed(storage, steps, warmup, lay=None):
+        s = make(storage, lay)
         s.step(warmup)
         s.sync()
         torch.cuda.synchronize()
@@ -465,6 +465,13 @@ def main():
                 v.update(errs(st))
             variants[P.STORAGE_NAMES[st]] = v
             print("[bench] %s: %.1f MLUPS" % (P.STORAGE_NAMES[st], m2), file=sys.stderr, flush=True)
+        # the same FP32 step with the other streaming layout (same algorithmic bytes)
+        other = P.LBM_AB if layout == P.LBM_AA else P.LBM_AA
+        w2, k2 = timed(P.LBM_F32, args.steps, args.warmup, other)
+        tag = "f32_" + ("ab" if other == P.LBM_AB else "aa")
+        variants[tag] = dict(mlups=round(N * args.steps / w2 / 1e6, 1), bytes_per_node=bpn,
+                             hbm_gbs_algorithmic=round(bpn * N / (k2 * 1e-3) / 1e9, 1))
+        print("[bench] %s: %.1f MLUPS" % (tag, variants[tag]["mlups"]), file=sys.stderr, flush=True)
 
     extras = {} if args.no_extras else run_extras(P, S, stream, torch)
 

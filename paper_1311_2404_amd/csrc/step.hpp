@@ -34,12 +34,12 @@
 // value is read once per step and written once, and is next touched only after ~2.5 GB
 // of other traffic.  Measured on the 256^3 step: +5% for FP32 stores.  Loads take it
 // where it pays:
-//  - AB: only populations with e_x = 0.  A wave's pull of an x-moving population starts
-//    one element off its 256-byte segment, so one 128-byte line is shared with the
-//    neighbouring wave; marked non-temporal, that line is often gone before the
-//    neighbour reads it (FETCH_SIZE 7.5% above the algorithmic bytes; exact without).
-//    +0.8% over hinting every load.
-//  - AA: every load (+7% over none, despite the refetch).
+//  - AB and the AA odd step: only populations with e_x = 0.  A wave's pull of an x-moving
+//    population starts one element off its 256-byte segment, so one 128-byte line is
+//    shared with the neighbouring wave; marked non-temporal, that line is often gone
+//    before the neighbour reads it (FETCH_SIZE 7.5% above the algorithmic bytes; exact
+//    without).  AB: +0.8% over hinting every load; AA: +1.3-1.6% (FP32, FP64).
+//  - AA even step: every load (all aligned; +7% over none).
 //  - 2-byte elements: none (the hint costs them 3-4%).
 // Build variants: LBM_PLAIN_LOADS and LBM_PLAIN_STORES remove the hint.
 template <class L, int LAYOUT, class T>
@@ -48,7 +48,7 @@ __device__ __forceinline__ T pop_load(const T *ptr, int i) {
     return *ptr;
 #else
     if constexpr (sizeof(T) < 4) return *ptr;
-    if (LAYOUT == lbm::LAYOUT_AB && L::ex(i) != 0) return *ptr;
+    if ((LAYOUT == lbm::LAYOUT_AB || LAYOUT == lbm::LAYOUT_AA_ODD) && L::ex(i) != 0) return *ptr;
     return __builtin_nontemporal_load(ptr);
 #endif
 }
