@@ -84,10 +84,11 @@ def rel(a, b):
 
 # ----------------------------------------------------------- C2: D3Q19 BGK 256^3 vortex
 
-@pytest.mark.parametrize("storage,tol", [(P.LBM_F64, 1e-12), (P.LBM_F32, 3e-6), (P.LBM_F32S, 3e-6),
-                                         (P.LBM_BF16S, 8e-3), (P.LBM_F16S, 1e-3)])
-def test_c2_fullsize_one_step_sampled(storage, tol):
-    got, want = one_step_sampled(c2_case(), storage)
+@pytest.mark.parametrize("storage,tol,layout", [(P.LBM_F64, 1e-12, P.LBM_AB), (P.LBM_F32, 3e-6, P.LBM_AB),
+                                                (P.LBM_F32, 3e-6, P.LBM_AA), (P.LBM_F32S, 3e-6, P.LBM_AB),
+                                                (P.LBM_BF16S, 8e-3, P.LBM_AB), (P.LBM_F16S, 1e-3, P.LBM_AB)])
+def test_c2_fullsize_one_step_sampled(storage, tol, layout):
+    got, want = one_step_sampled(c2_case(), storage, layout=layout)
     assert rel(got, want) <= tol, (P.STORAGE_NAMES[storage], rel(got, want))
 
 
@@ -110,6 +111,12 @@ def test_c2_fullsize_1000_steps_decay_and_conservation():
         law = np.exp(-6 * c.extra["nu"] * k * k * 1000)
         assert abs(d1[5] / d0[5] - law) <= 5e-3 * law
     assert rel(runs[P.LBM_F32], runs[P.LBM_F64]) <= 1e-5
+    # the timed configuration streams in place (AA): the same 1000 steps, bit for bit
+    s = P.Sim.from_case(c, P.LBM_F32, P.LBM_AA)
+    s.step(1000)
+    u_aa = s.macro()[1]
+    s.close()
+    assert np.array_equal(u_aa, runs[P.LBM_F32])
 
 
 # ----------------------------------------------------------- C3: D3Q19 MRT duct 128x128x512
