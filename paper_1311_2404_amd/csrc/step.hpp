@@ -40,14 +40,18 @@
 //    before the neighbour reads it (FETCH_SIZE 7.5% above the algorithmic bytes; exact
 //    without).  AB: +0.8% over hinting every load; AA: +1.3-1.6% (FP32, FP64).
 //  - AA even step: every load (all aligned; +7% over none).
-//  - 2-byte elements: none (the hint costs them 3-4%).
+//  - 2-byte elements: only in the AA even step, where every access is aligned (+13% on
+//    the BF16 256^3 step); elsewhere the hint costs them 3-4%.
 // Build variants: LBM_PLAIN_LOADS and LBM_PLAIN_STORES remove the hint.
 template <class L, int LAYOUT, class T>
 __device__ __forceinline__ T pop_load(const T *ptr, int i) {
 #if defined(LBM_PLAIN_LOADS)
     return *ptr;
 #else
-    if constexpr (sizeof(T) < 4) return *ptr;
+    if constexpr (sizeof(T) < 4) {
+        if (LAYOUT == lbm::LAYOUT_AA_EVEN) return __builtin_nontemporal_load(ptr);
+        return *ptr;
+    }
     if ((LAYOUT == lbm::LAYOUT_AB || LAYOUT == lbm::LAYOUT_AA_ODD) && L::ex(i) != 0) return *ptr;
     return __builtin_nontemporal_load(ptr);
 #endif
