@@ -2,7 +2,7 @@
 //
 // The network (6 -> 32 -> 32 -> 1, tanh hidden units) adds its output to the series
 // estimate 2 + (a3 - 2 a4)/(3 a2) of the entropic alpha to propose the first Newton
-// iterate; Newton remains the judge of the result.  Training minimises the squared
+// iterate; Newton still decides the result.  Training minimises the squared
 // error of the proposal, i.e. of the network against the series residual alpha - base,
 // which is formed in FP64 so that the small residual is not lost to FP32 rounding.
 // Training is plain minibatch MSE with Adam in FP32; gradients are reduced across a

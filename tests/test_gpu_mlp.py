@@ -154,7 +154,7 @@ def _mean_iters(hist):
 
 def test_trained_mlp_cuts_newton_iterations():
     """Train on (state, alpha) pairs the plain solver produces, then run the same steps
-    from the same state with alpha0 = 2 and with alpha0 = MLP: Newton stays the judge, so
+    from the same state with alpha0 = 2 and with alpha0 = MLP: Newton still decides alpha, so
     the fields agree to the Newton tolerance while the MLP start needs fewer iterations."""
     c = elbm_case(32, u0=0.1, nu=2e-4, noise=5e-4)
     s = P.Sim.from_case(c, P.LBM_F64, P.LBM_AB)
