@@ -61,6 +61,8 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F32S = 2, LBM_BF16S = 3, LBM_F16S = 4 };
 /* Streaming pattern (GPU-algorithms subsection): AB = two copies, ping-pong;
  * AA = one copy updated in place, even and odd steps access different slots. */
 enum { LBM_AB = 0, LBM_AA = 1 };
+/* Population layouts in HBM (lbm_set_pop_layout). */
+enum { LBM_POP_TILED = 0, LBM_POP_SOA = 1 };
 /* uint8 node flags (boundary-conditions subsection): fluid; full-way bounce-back wall (a
  * dry node that returns what it receives); equilibrium velocity node (a fluid node on a
  * domain face whose populations streamed in from wall nodes are missing: each takes the
@@ -93,6 +95,22 @@ int lbm_create(int lattice, int model, int nx, int ny, int nz, double tau,
  * rounds BF16/F16 stores stochastically (counter-hash seeded, unbiased) instead of to
  * nearest even.  Only before the first init; default LBM_F32, LBM_AB, round to nearest. */
 int lbm_set_storage(lbm_sim *sim, int storage, int layout, int stochastic_round);
+
+/* Population layout in HBM.  Only before the first init; the results do not depend on
+ * it (every layout gives the same fields bit for bit), only the speed does.
+ *  - LBM_POP_TILED (default): f[z][y/TY][c][q][y%TY][x].  Each x row of each population
+ *    is a run of nx elements rounded up to 256 bytes, plus row_pad bytes; the C*Q runs of
+ *    TY = tile_rows consecutive rows lie together, followed by block_pad bytes.
+ *    tile_rows 0 means 8; otherwise a power of two from 1 to 64.  block_pad -1 means
+ *    1024.  TY is halved while half of it still covers ny.  Grids whose tiled layout
+ *    would not fit 32-bit element offsets fall back to LBM_POP_SOA.
+ *  - LBM_POP_SOA: the structure of arrays f[c][q][z][y][x] of the paper's GPU data
+ *    layout; consecutive population arrays are N elements apart, rounded up to 256
+ *    bytes, plus soa_pad bytes (-1 means 17 * 256).
+ * Pads are rounded down to whole 256 bytes and must lie in [0, 1 MiB].  Arguments that
+ * do not apply to the chosen kind are checked and ignored.  Bad values: LBM_EINVAL. */
+int lbm_set_pop_layout(lbm_sim *sim, int kind, int tile_rows, int64_t row_pad, int64_t block_pad,
+                       int64_t soa_pad);
 
 /* MRT relaxation rates s[q], q = 9 or 19, in the moment order of the orthogonal basis
  * of d'Humieres et al. (2002) that the MRT subsection cites: D3Q19 rows 1, e, eps,
@@ -159,7 +177,10 @@ int lbm_init_eq(lbm_sim *sim, const double *rho, const double *u, const double *
 int lbm_set_f(lbm_sim *sim, const double *f);
 int lbm_get_f(lbm_sim *sim, double *f);
 
-/* Enqueue n >= 0 time steps on the handle's stream (asynchronous). */
+/* Enqueue n >= 0 time steps on the handle's stream (asynchronous).  A step kernel that
+ * produces a non-finite population raises a device flag; the next lbm_sync() reads it and
+ * returns LBM_EDIVERGED.  From then on lbm_step() returns LBM_EDIVERGED without
+ * enqueuing anything, until lbm_init_eq() or lbm_set_f() gives the handle a new state. */
 int lbm_step(lbm_sim *sim, int n);
 
 /* Macroscopic fields of the current state into host FP64 arrays rho[C][N] and
@@ -230,7 +251,8 @@ int lbm_mlp_forward(lbm_sim *sim, const void *feat_dev, int64_t n, void *y_dev);
 /* Steps taken since the last init / set_f. */
 int lbm_steps_done(const lbm_sim *sim, int64_t *steps);
 
-/* Wait for the handle's stream. */
+/* Wait for the handle's stream.  Returns LBM_EDIVERGED if a step since the last init
+ * produced a non-finite population (see lbm_step). */
 int lbm_sync(lbm_sim *sim);
 
 /* Message for the last error on this handle (or of the calling thread when sim is NULL). */

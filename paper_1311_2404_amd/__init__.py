@@ -21,6 +21,7 @@ LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_BGK, LBM_MRT, LBM_ELBM, LBM_SHANCHEN, LBM_REGULARIZED, LBM_SMAGORINSKY, LBM_FREE_ENERGY = 0, 1, 2, 3, 4, 5, 6
 LBM_F64, LBM_F32, LBM_F32S, LBM_BF16S, LBM_F16S = 0, 1, 2, 3, 4
 LBM_AB, LBM_AA = 0, 1
+LBM_POP_TILED, LBM_POP_SOA = 0, 1
 LBM_FLUID, LBM_WALL_BB, LBM_VELOCITY, LBM_HALFWAY_BB = 0, 1, 2, 3
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSUPPORTED, LBM_EDIVERGED = 0, -1, -2, -3, -4, -5, -6
 MLP_NPARAM = 1313
@@ -33,6 +34,7 @@ _vp, _dp, _fp, _i64 = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_float), C
 _SIGS = [
     ("lbm_create", C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _dp, C.POINTER(_vp)]),
     ("lbm_set_storage", C.c_int, [_vp, C.c_int, C.c_int, C.c_int]),
+    ("lbm_set_pop_layout", C.c_int, [_vp, C.c_int, C.c_int, _i64, _i64, _i64]),
     ("lbm_set_mrt_rates", C.c_int, [_vp, _dp, C.c_int]),
     ("lbm_set_elbm", C.c_int, [_vp, C.c_int, C.c_double, C.c_int]),
     ("lbm_set_shanchen", C.c_int, [_vp, C.c_double, C.c_int]),
@@ -132,6 +134,10 @@ def lbm_create(lattice, model, nx, ny, nz, tau, force=None):
 
 def lbm_set_storage(sim, storage, layout=LBM_AB, stochastic_round=0):
     _err(sim, lib().lbm_set_storage(sim, storage, layout, int(stochastic_round)))
+
+
+def lbm_set_pop_layout(sim, kind=LBM_POP_TILED, tile_rows=0, row_pad=0, block_pad=-1, soa_pad=-1):
+    _err(sim, lib().lbm_set_pop_layout(sim, kind, tile_rows, row_pad, block_pad, soa_pad))
 
 
 def lbm_set_mrt_rates(sim, s):
@@ -296,7 +302,7 @@ class Sim:
     """One simulation handle.  ``stream`` defaults to torch's current stream."""
 
     def __init__(self, lattice, model, nx, ny, nz, tau, force=None, storage=LBM_F32, layout=LBM_AB,
-                 stochastic_round=0, stream="current"):
+                 stochastic_round=0, stream="current", pop_layout=None):
         self.lattice, self.model = lattice, model
         self.nx, self.ny, self.nz = nx, ny, nz
         self.q = 9 if lattice == LBM_D2Q9 else 19
@@ -306,6 +312,8 @@ class Sim:
         self.storage = storage
         self.h = lbm_create(lattice, model, nx, ny, nz, tau, force)
         lbm_set_storage(self.h, storage, layout, stochastic_round)
+        if pop_layout is not None:
+            lbm_set_pop_layout(self.h, **pop_layout)
         if stream == "current":
             import torch
             if torch.cuda.is_available():

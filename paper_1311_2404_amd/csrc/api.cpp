@@ -48,6 +48,12 @@ struct lbm_sim {
     double *macro_d = nullptr;  // FP64 rho[C][N] + u[3][N] scratch for lbm_macro / lbm_diag
     double *red_d = nullptr;    // diag partials + result
     unsigned int *bad_d = nullptr;
+    unsigned int *div_d = nullptr;  // raised by a step kernel that produced a non-finite population
+    bool diverged = false;          // a synchronising call has seen that flag since the last init
+    // population layout (lbm_set_pop_layout): row-interleaved tiles or SoA, tile height
+    // (log2, -1 = default), pads in bytes (-1 = default)
+    int pop_kind = 0, pop_tyl = -1;
+    int64_t row_pad = 0, block_pad = -1, soa_pad = -1;
     uint16_t *mlp_bf16 = nullptr;
     float *mlp_wf_d = nullptr;  // BF16 weights widened to FP32, then mu[6], isd[6]
     uint32_t *mlp_lane_d = nullptr;  // per-lane MFMA operand table (64 x 44 words)
@@ -89,9 +95,7 @@ int hip_fail(lbm_sim *s, hipError_t e, const char *where) {
         if (e_ != hipSuccess) return hip_fail(sim, e_, #expr); \
     } while (0)
 
-// population layout used unless LBM_POP_LAYOUT overrides it (see pop_geometry)
-constexpr bool POP_ROWS_DEFAULT = true;
-constexpr int POP_TILE_LOG2_DEFAULT = 3;  // rows per population run: 2^this
+constexpr int POP_TILE_LOG2_DEFAULT = 3;  // rows per population run of the tiled layout: 2^this
 
 size_t elem_size(int storage) {
     switch (storage) {
@@ -163,14 +167,11 @@ StepParams base_params(const lbm_sim *s) {
     p.G = s->G;
     p.psi_mode = s->psi_mode;
     p.seed = s->seed;
+    p.diverged = s->div_d;
     return p;
 }
 
 // Population layout.  Two are built:
-//  - SoA, f[c][q][z][y][x]: slot stride S = N rounded up to whole 256-byte units plus a
-//    pad of 17 such units, so that the Q population arrays do not start at addresses
-//    that differ by a large power of two (which maps the 2Q streams of a row onto the
-//    same HBM channels; measured +1 to +3% on the 256^3 step); row pitch nx.
 //  - row-interleaved, f[z][y/TY][c][q][y%TY][x] (TY = 2^tyl rows per tile, 8 by default;
 //    ceil(ny/TY) tiles per z plane, the last one padded with rows that are never
 //    addressed when TY does not divide ny: 254 rows cost 0.8% more memory and keep the
@@ -183,29 +184,23 @@ StepParams base_params(const lbm_sim *s) {
 //    FP32 +5 to +7%, FP64 +5%, the MRT duct +4%, Shan-Chen +4%; the 1 KB between row
 //    blocks adds ~1% for FP32 and FP64 (0, 2, 3, 4, 5, 8 and 13 KB measured).
 //    This is the default.
-// LBM_POP_LAYOUT=soa|rows selects one; LBM_POP_PAD overrides the SoA pad,
-// LBM_ROW_PAD adds to RP and LBM_BLOCK_PAD to the tile pitch (bytes, rounded down to
-// 256); LBM_ROW_TILE sets TY (rounded down to a power of two).  TY shrinks only while
-// half of it still covers ny, so a short ny wastes less than half its tile.
+//  - SoA, f[c][q][z][y][x] (the paper's structure of arrays): slot stride S = N rounded
+//    up to whole 256-byte units plus a pad of 17 such units, so that the Q population
+//    arrays do not start at addresses that differ by a large power of two (which maps
+//    the 2Q streams of a row onto the same HBM channels; measured +1 to +3% on the 256^3
+//    step); row pitch nx.  Also taken when the tiled layout would not fit 32-bit offsets.
+// lbm_set_pop_layout selects one and sets the tile height and the pads.  TY shrinks only
+// while half of it still covers ny, so a short ny wastes less than half its tile.
 void pop_geometry(lbm_sim *s) {
     const uint64_t align = 256 / elem_size(s->storage);
     const uint64_t cq = uint64_t(s->C) * s->Q;
-    uint64_t RP = (uint64_t(s->nx) + align - 1) / align * align;
-    if (const char *e = std::getenv("LBM_ROW_PAD")) RP += std::strtoull(e, nullptr, 10) / 256 * align;
-    bool interleave = POP_ROWS_DEFAULT;
-    if (const char *e = std::getenv("LBM_POP_LAYOUT")) interleave = std::strcmp(e, "rows") == 0;
-    int tyl = POP_TILE_LOG2_DEFAULT;
-    if (const char *e = std::getenv("LBM_ROW_TILE")) {
-        const int ty = std::atoi(e);
-        tyl = 0;
-        while ((2 << tyl) <= ty && tyl < 6) tyl++;
-    }
+    const uint64_t RP = (uint64_t(s->nx) + align - 1) / align * align + uint64_t(s->row_pad) / 256 * align;
+    int tyl = s->pop_tyl >= 0 ? s->pop_tyl : POP_TILE_LOG2_DEFAULT;
     while (tyl > 0 && (1 << (tyl - 1)) >= s->ny) tyl--;
     const uint64_t ty = uint64_t(1) << tyl, tiles = (uint64_t(s->ny) + ty - 1) / ty * s->nz;
-    uint64_t block = cq * ty * RP, block_pad = 1024;
-    if (const char *e = std::getenv("LBM_BLOCK_PAD")) block_pad = std::strtoull(e, nullptr, 10);
-    block += block_pad / 256 * align;
-    if (interleave && tiles * block < (uint64_t(1) << 32)) {
+    const uint64_t block_pad = s->block_pad >= 0 ? uint64_t(s->block_pad) : 1024;
+    const uint64_t block = cq * ty * RP + block_pad / 256 * align;
+    if (s->pop_kind == LBM_POP_TILED && tiles * block < (uint64_t(1) << 32)) {
         s->S = uint32_t(ty * RP);
         s->rp = uint32_t(block);
         s->rpitch = uint32_t(RP);
@@ -213,10 +208,8 @@ void pop_geometry(lbm_sim *s) {
         s->pop_elems = size_t(tiles * block);
         return;
     }
-    uint64_t S = (uint64_t(s->N) + align - 1) / align * align;
-    uint64_t pad_bytes = 17 * 256;
-    if (const char *e = std::getenv("LBM_POP_PAD")) pad_bytes = std::strtoull(e, nullptr, 10);
-    S += pad_bytes / 256 * align;
+    const uint64_t pad_bytes = s->soa_pad >= 0 ? uint64_t(s->soa_pad) : 17 * 256;
+    const uint64_t S = (uint64_t(s->N) + align - 1) / align * align + pad_bytes / 256 * align;
     s->S = S >= (uint64_t(1) << 32) ? s->N : uint32_t(S);
     s->rp = uint32_t(s->nx);
     s->rpitch = 0;
@@ -235,6 +228,8 @@ int ensure_alloc(lbm_sim *s) {
     if (s->model == LBM_SHANCHEN || s->model == LBM_FREE_ENERGY)
         HIPCHK(s, hipMalloc(&s->psi_d, 2 * size_t(s->N) * compute_size(s->storage)));
     HIPCHK(s, hipMalloc(&s->bad_d, sizeof(unsigned int)));
+    HIPCHK(s, hipMalloc(&s->div_d, sizeof(unsigned int)));
+    HIPCHK(s, hipMemsetAsync(s->div_d, 0, sizeof(unsigned int), s->stream));
     HIPCHK(s, hipMalloc(&s->stats_d, sizeof(unsigned long long) * (NEWTON_BINS + 1)));
     HIPCHK(s, hipMemsetAsync(s->stats_d, 0, sizeof(unsigned long long) * (NEWTON_BINS + 1), s->stream));
     if (!s->flags_d) {
@@ -378,6 +373,28 @@ int lbm_set_storage(lbm_sim *s, int storage, int layout, int stochastic_round) {
     return LBM_OK;
 }
 
+int lbm_set_pop_layout(lbm_sim *s, int kind, int tile_rows, int64_t row_pad, int64_t block_pad, int64_t soa_pad) {
+    if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
+    if (s->ready) return fail(s, LBM_ESTATE, "the population layout can only be set before the first init");
+    if (kind != LBM_POP_TILED && kind != LBM_POP_SOA) return fail(s, LBM_EINVAL, "unknown population layout");
+    if (tile_rows != 0 && (tile_rows < 1 || tile_rows > 64 || (tile_rows & (tile_rows - 1)) != 0))
+        return fail(s, LBM_EINVAL, "tile_rows must be 0 (default) or a power of two from 1 to 64");
+    const int64_t lim = int64_t(1) << 20;
+    if (row_pad < 0 || row_pad > lim || block_pad < -1 || block_pad > lim || soa_pad < -1 || soa_pad > lim)
+        return fail(s, LBM_EINVAL, "pads must lie in [0, 1 MiB] (-1: default for block_pad and soa_pad)");
+    int tyl = -1;
+    if (tile_rows) {
+        tyl = 0;
+        while ((1 << tyl) < tile_rows) tyl++;
+    }
+    s->pop_kind = kind;
+    s->pop_tyl = tyl;
+    s->row_pad = row_pad;
+    s->block_pad = block_pad;
+    s->soa_pad = soa_pad;
+    return LBM_OK;
+}
+
 int lbm_set_mrt_rates(lbm_sim *s, const double *rates, int q) {
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
     if (!rates || q != s->Q) return fail(s, LBM_EINVAL, "rates must hold Q values");
@@ -485,6 +502,8 @@ int lbm_init_eq(lbm_sim *s, const double *rho, const double *u, const double *df
     HIPCHK(s, hipMemcpyAsync(u_d, u, sizeof(double) * s->D * N, hipMemcpyHostToDevice, s->stream));
     s->steps = 0;
     s->cur = 0;
+    s->diverged = false;
+    HIPCHK(s, hipMemsetAsync(s->div_d, 0, sizeof(unsigned int), s->stream));
     const LaunchCfg cfg = node_cfg(s);
     for (int c = 0; c < s->C; c++)
         for (int q = 0; q < s->Q; q++) {
@@ -520,6 +539,8 @@ int lbm_set_f(lbm_sim *s, const double *f) {
     if (rc) return rc;
     s->steps = 0;
     s->cur = 0;
+    s->diverged = false;
+    HIPCHK(s, hipMemsetAsync(s->div_d, 0, sizeof(unsigned int), s->stream));
     const LaunchCfg cfg = node_cfg(s);
     for (int c = 0; c < s->C; c++)
         for (int q = 0; q < s->Q; q++) {
@@ -554,6 +575,9 @@ int lbm_step(lbm_sim *s, int n) {
     if (!s->ready) return fail(s, LBM_ESTATE, "no state yet: call lbm_init_eq or lbm_set_f");
     if (s->model == LBM_ELBM && s->alpha_init == 2 && !s->mlp_set)
         return fail(s, LBM_ESTATE, "alpha_init = MLP needs lbm_mlp_set_weights first");
+    if (s->diverged)
+        return fail(s, LBM_EDIVERGED, "the state has diverged (a step produced a non-finite population); "
+                                      "re-initialise it with lbm_init_eq or lbm_set_f");
     const LaunchCfg cfg = node_cfg(s);
     StepParams p = base_params(s);
     for (int k = 0; k < n; k++) {
@@ -654,6 +678,13 @@ int lbm_steps_done(const lbm_sim *s, int64_t *steps) {
 int lbm_sync(lbm_sim *s) {
     if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
     HIPCHK(s, hipStreamSynchronize(s->stream));
+    if (s->ready && !s->diverged) {
+        unsigned int flag = 0;
+        HIPCHK(s, hipMemcpy(&flag, s->div_d, sizeof(flag), hipMemcpyDeviceToHost));
+        s->diverged = flag != 0;
+    }
+    if (s->diverged)
+        return fail(s, LBM_EDIVERGED, "a step produced a non-finite population (diverged state)");
     return LBM_OK;
 }
 
@@ -662,7 +693,7 @@ const char *lbm_last_error(const lbm_sim *s) { return s ? s->err.c_str() : t_err
 void lbm_destroy(lbm_sim *s) {
     if (!s) return;
     if (s->ready || s->flags_d) (void)hipStreamSynchronize(s->stream);
-    void *ptrs[] = {s->buf[0], s->buf[1], s->flags_d, s->psi_d, s->stage, s->macro_d, s->red_d, s->bad_d,
+    void *ptrs[] = {s->buf[0], s->buf[1], s->flags_d, s->psi_d, s->stage, s->macro_d, s->red_d, s->bad_d, s->div_d,
                     s->mlp_bf16, s->mlp_wf_d, s->mlp_lane_d, s->stats_d, s->mlp_w_d, s->mlp_m_d, s->mlp_v_d, s->mlp_g_d,
                     s->mlp_norm_d, s->mlp_tnorm_d, s->mlp_part_d, s->mlp_acc_d};
     for (void *p : ptrs)

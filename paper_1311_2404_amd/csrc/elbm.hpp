@@ -25,6 +25,17 @@
 // |d| <= 0.1, so g(2.5) > 0).  On that bracket the Newton iteration needs only the 16
 // moments, computed once, and two Horner chains per step: no logarithm per iteration.
 // Nodes with m > 0.1 take the logarithmic form above.
+//
+// Order of the series.  The cut after k = K moves the root by about
+// alpha^2 (alpha m)^(K-1) / (K (K+1)) (an upper bound, 4-5x above what random D3Q19
+// states show), so (with alpha ~ 2) its effect on a population, that times m, stays below
+// eps_C when 4 (2m)^(K-1) m / (K (K+1)) <= eps_C.  The common case of a resolved flow has
+// m ~ 1e-3 and needs only K = 6, a third of the FP64 work of K = 16.  A wave therefore
+// takes K = 6 when all its nodes have m <= m6 (m6 = 3.8e-3 for FP64 compute, with
+// eps = 1e-14; 1.2e-2 for FP32 compute, with eps = 1e-11, far below FP32 rounding) and
+// K = 16 otherwise.  The choice is wave-uniform (one ballot), so both orders are fully
+// unrolled register code.  It is made before the FP64 pass, from the exact test
+// |D_i| > m6 (w_i + h_i) in compute precision (three instructions per population).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -42,7 +53,14 @@ struct AlphaOut {
 
 constexpr double ALPHA_SHORTCUT = 1e-6;
 constexpr int ALPHA_K = 16;               // highest moment of the power-series form
+constexpr int ALPHA_K_LO = 6;             // the order of waves whose nodes all have m <= m6
 constexpr double ALPHA_SERIES_DMAX = 0.1; // largest max |d_i| handled by that form
+
+// m6 of the compute type C (see the order of the series above)
+template <class C>
+__device__ __forceinline__ constexpr double alpha_m6() {
+    return sizeof(C) == 8 ? 3.8e-3 : 1.2e-2;
+}
 
 // Per-node summary of the alpha problem, built from h = f - w and heq = feq - w (the
 // shifted populations the collision holds in registers), so that the solve keeps no
@@ -58,7 +76,8 @@ struct AlphaNode {
     double dm, jx, jy, jz;    // mass and momentum removed from D
     double dmax, amax;        // max |d_i|; largest step keeping f + a D positive
     double mneg, mpos;        // max(-d_i), max(d_i)
-    double am[ALPHA_K + 1];   // am[k] = sum_i f_i d_i^k, k = 1..ALPHA_K
+    double am[ALPHA_K + 1];   // am[k] = sum_i f_i d_i^k, k = 1..K (K = ALPHA_K_LO or ALPHA_K)
+    bool khi;                 // the wave takes K = ALPHA_K (wave-uniform)
 };
 
 template <class L, class C>
@@ -67,12 +86,28 @@ __device__ __forceinline__ double alpha_D(const C *h, const C *heq, const AlphaN
            L::w(i) * (s.dm + 3.0 * (L::ex(i) * s.jx + L::ey(i) * s.jy + L::ez(i) * s.jz));
 }
 
-// 1/f in FP64: the hardware reciprocal refined by two Newton steps (each doubles the
-// correct bits), about half the instructions of a correctly rounded division.
+// 1/f in FP64: the hardware reciprocal (2^-23 relative) refined by Newton steps, each of
+// which doubles the correct bits: two for FP64 compute (full precision), one for FP32
+// compute (2^-46, far below what FP32 populations resolve).  About half the
+// instructions of a correctly rounded division.
+template <class C = double>
 __device__ __forceinline__ double recip(double f) {
     double r = __builtin_amdgcn_rcp(f);
     r = fma(r, fma(-f, r, 1.0), r);
-    return fma(r, fma(-f, r, 1.0), r);
+    if constexpr (sizeof(C) == 8) r = fma(r, fma(-f, r, 1.0), r);
+    return r;
+}
+
+// Order of the series for this wave: K = ALPHA_K unless every node of the wave has
+// |heq_i - h_i| <= m6 (w_i + h_i) for all i (wave-uniform; lanes that do not take part
+// are not counted).
+template <class L, class C>
+__device__ __forceinline__ bool alpha_needs_khi(const C *h, const C *heq) {
+    const C m6 = C(alpha_m6<C>());
+    bool big = false;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) big |= fabs(heq[i] - h[i]) > fma(m6, h[i], C(m6 * L::w(i)));
+    return __builtin_amdgcn_ballot_w64(big) != 0;
 }
 
 // the raw mass and momentum of heq - h (removed from D by alpha_D)
@@ -111,7 +146,7 @@ __device__ __forceinline__ double alpha_feature_pass(const C *h, const C *heq, c
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
         const double D = alpha_D<L, C>(h, heq, s, i);
-        const double d = D * recip(L::w(i) + double(h[i]));
+        const double d = D * recip<C>(L::w(i) + double(h[i]));
         double t = D * d;
         a2 += t;
         t *= d;
@@ -127,8 +162,8 @@ __device__ __forceinline__ double alpha_feature_pass(const C *h, const C *heq, c
 }
 
 // max |d|, max(-d), max(d), a_max and the moments a_1..a_K, after alpha_project
-template <class L, class C>
-__device__ __forceinline__ void alpha_moments(const C *h, const C *heq, AlphaNode &s) {
+template <class L, class C, int K>
+__device__ __forceinline__ void alpha_moments_k(const C *h, const C *heq, AlphaNode &s) {
     s.dmax = 0.0;
     s.mneg = s.mpos = -1e300;
 #pragma unroll
@@ -136,20 +171,28 @@ __device__ __forceinline__ void alpha_moments(const C *h, const C *heq, AlphaNod
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
         const double D = alpha_D<L, C>(h, heq, s, i);
-        const double d = D * recip(L::w(i) + double(h[i]));
+        const double d = D * recip<C>(L::w(i) + double(h[i]));
         s.dmax = fmax(s.dmax, fabs(d));
         s.mneg = fmax(s.mneg, -d);
         s.mpos = fmax(s.mpos, d);
         double t = D;  // f_i d_i
         s.am[1] += t;
 #pragma unroll
-        for (int k = 2; k <= ALPHA_K; k++) {
+        for (int k = 2; k <= K; k++) {
             t *= d;
             s.am[k] += t;
         }
     }
     // min over d_i < 0 of -1/d_i is 1 / max(-d_i)
     s.amax = s.mneg > 0.0 ? 1.0 / s.mneg : INFINITY;
+}
+
+// the order of the wave, then its moments (after alpha_project)
+template <class L, class C>
+__device__ __forceinline__ void alpha_moments(const C *h, const C *heq, AlphaNode &s) {
+    s.khi = alpha_needs_khi<L, C>(h, heq);
+    if (s.khi) alpha_moments_k<L, C, ALPHA_K>(h, heq, s);
+    else alpha_moments_k<L, C, ALPHA_K_LO>(h, heq, s);
 }
 
 template <class L, class C>
@@ -170,7 +213,7 @@ __device__ __forceinline__ AlphaOut alpha_newton_log(const C *h, const C *heq, c
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
         fl[i] = L::w(i) + double(h[i]);
-        dl[i] = alpha_D<L, C>(h, heq, s, i) * recip(fl[i]);
+        dl[i] = alpha_D<L, C>(h, heq, s, i) * recip<C>(fl[i]);
     }
     double lo = 1.0, hi = s.amax, a = a0;
     if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
@@ -198,15 +241,16 @@ __device__ __forceinline__ AlphaOut alpha_newton_log(const C *h, const C *heq, c
     return {fmin(2.0, 0.99 * s.amax), maxit, 0};
 }
 
-// Newton with bisection safeguard on g in its power-series form.  am[k] = a_k for
-// k = 1..ALPHA_K; bracket [1, hi] with hi <= 2.5 (see above).
+// Newton with bisection safeguard on g in its power-series form of order K.  am[k] = a_k
+// for k = 1..K; bracket [1, hi] with hi <= 2.5 (see above).
+template <int K>
 __device__ __forceinline__ AlphaOut alpha_newton_moments(const double *am, double a0, double hi, double tol,
                                                          int maxit) {
     // g(x) = x (S1(x) - B), g'(x) = S2(x) - B with S1 = sum_k c_k x^(k-1),
     // S2 = sum_k k c_k x^(k-1), c_k = (-1)^k a_k / (k (k-1)), B = sum_k (-1)^k a_k/(k-1) - a_1
-    double c[ALPHA_K + 1], B = -am[1];
+    double c[K + 1], B = -am[1];
 #pragma unroll
-    for (int k = 2; k <= ALPHA_K; k++) {
+    for (int k = 2; k <= K; k++) {
         const double sk = (k & 1) ? -am[k] : am[k];
         c[k] = sk * (1.0 / double(k * (k - 1)));
         B += sk * (1.0 / double(k - 1));
@@ -214,9 +258,9 @@ __device__ __forceinline__ AlphaOut alpha_newton_moments(const double *am, doubl
     double lo = 1.0, x = a0;
     if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
     for (int it = 1; it <= maxit; it++) {
-        double s1 = c[ALPHA_K], s2 = double(ALPHA_K) * c[ALPHA_K];
+        double s1 = c[K], s2 = double(K) * c[K];
 #pragma unroll
-        for (int k = ALPHA_K - 1; k >= 2; k--) {
+        for (int k = K - 1; k >= 2; k--) {
             s1 = fma(s1, x, c[k]);
             s2 = fma(s2, x, double(k) * c[k]);
         }
@@ -334,7 +378,10 @@ __device__ __forceinline__ float mlp_eval_wave(const uint32_t *__restrict__ lane
 template <class L, class C>
 __device__ __forceinline__ AlphaOut alpha_root(const C *h, const C *heq, const AlphaNode &s, double a0, double tol,
                                                int maxit) {
-    if (s.dmax <= ALPHA_SERIES_DMAX) return alpha_newton_moments(s.am, a0, 2.5, tol, maxit);
+    if (s.dmax <= ALPHA_SERIES_DMAX) {
+        if (s.khi) return alpha_newton_moments<ALPHA_K>(s.am, a0, 2.5, tol, maxit);
+        return alpha_newton_moments<ALPHA_K_LO>(s.am, a0, 2.5, tol, maxit);
+    }
     return alpha_newton_log<L, C>(h, heq, s, a0, tol, maxit);
 }
 

@@ -53,6 +53,7 @@ struct StepParams {
     // stochastic rounding stream
     uint32_t seed;
     uint32_t step;
+    unsigned int *diverged;     // raised by a step that produces a non-finite population
 };
 
 }  // namespace lbm

@@ -20,10 +20,6 @@
 
 #include <type_traits>
 
-#ifndef LBM_WIDE_ADDR
-#define LBM_WIDE_ADDR 0  // build variant: 1 gives 2-byte elements the per-lane address too
-#endif
-
 #include "collide.hpp"
 #include "elbm.hpp"
 #include "lattice.hpp"
@@ -42,42 +38,39 @@
 //  - AA even step: every load (all aligned; +7% over none).
 //  - 2-byte elements: only in the AA even step, where every access is aligned (+13% on
 //    the BF16 256^3 step); elsewhere the hint costs them 3-4%.
-// Build variants: LBM_PLAIN_LOADS and LBM_PLAIN_STORES remove the hint.
 template <class L, int LAYOUT, class T>
 __device__ __forceinline__ T pop_load(const T *ptr, int i) {
-#if defined(LBM_PLAIN_LOADS)
-    return *ptr;
-#else
     if constexpr (sizeof(T) < 4) {
         if (LAYOUT == lbm::LAYOUT_AA_EVEN) return __builtin_nontemporal_load(ptr);
         return *ptr;
     }
     if ((LAYOUT == lbm::LAYOUT_AB || LAYOUT == lbm::LAYOUT_AA_ODD) && L::ex(i) != 0) return *ptr;
     return __builtin_nontemporal_load(ptr);
-#endif
 }
 #define LBM_LOAD(ptr, i) pop_load<L, LAYOUT>((ptr), (i))
-#if defined(LBM_PLAIN_STORES)
-#define LBM_STORE(ptr, v) (*(ptr) = (v))
-#else
 #define LBM_STORE(ptr, v) __builtin_nontemporal_store((v), (ptr))
-#endif
 // Stores of population i.  The AA odd step writes x-moving populations one element off
 // the wave's 256-byte segment, so each wave leaves a partly written 64-byte sector at
 // both ends that the neighbouring wave completes.  Those stores go without the hint: the
 // line then waits in L2 for its other half instead of reaching HBM as a partial write.
 template <class L, int LAYOUT, class T>
 __device__ __forceinline__ void pop_store(T *ptr, T v, int i) {
-#if defined(LBM_PLAIN_STORES)
-    *ptr = v;
-#else
     if (LAYOUT == lbm::LAYOUT_AA_ODD && L::ex(i) != 0) *ptr = v;
     else __builtin_nontemporal_store(v, ptr);
-#endif
 }
 #define LBM_STORE_POP(ptr, v, i) pop_store<L, LAYOUT>((ptr), (v), (i))
 
 namespace lbm {
+
+// Divergence flag of a step: a node whose post-collision rest population is not finite
+// raises *p.diverged, which the next synchronising call of the library reads back.  The
+// rest population is formed from the node's mass (the conservation restore, or the
+// free-energy rest equation), so a non-finite population or moment anywhere in the node
+// reaches it: one class test per node.
+template <class C>
+__device__ __forceinline__ void note_nonfinite(const StepParams &p, C v) {
+    if (!__builtin_isfinite(v)) *p.diverged = 1u;
+}
 
 // A node and its periodic neighbours.  at() is the linear node index (flags, psi,
 // macroscopic fields); pa() is the node's offset inside one population's block, which
@@ -156,7 +149,7 @@ __device__ __forceinline__ void post_dir(int layout, int i, int &slot, int &dx, 
 // elements, which are bound by memory, the plain per-lane 64-bit address is ~1% faster.
 template <class T>
 __device__ __forceinline__ T *pop_addr(T *base, uint32_t S, int slot, const Geo &g, int dx, int dy, int dz) {
-    if constexpr (sizeof(T) == 2 && !LBM_WIDE_ADDR) {
+    if constexpr (sizeof(T) == 2) {
         T *row = base + (size_t(slot) * S + g.row_off(dy, dz));
         using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
         return reinterpret_cast<T *>(reinterpret_cast<B *>(row) + g.x_of(dx) * uint32_t(sizeof(T)));
@@ -322,6 +315,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                     if (!ao.converged) atomicAdd(&s_hist[NEWTON_BINS], 1u);
                 }
             }
+            note_nonfinite<C>(p, o[0]);
             // stochastic rounding reads the top 16 bits of rnd: one draw serves two values
             SrStream rs{0u};
             uint32_t draw = 0;
@@ -355,7 +349,8 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
 
 // The entropic step with the MLP first guess.  The network runs on the matrix cores for
 // the 64 nodes of a wave at once (mlp_eval_wave), which needs every lane of the wave at
-// that point: so this kernel does not branch around it.  Lanes past the end of a row
+// that point: so this kernel does not branch around it per lane, only per wave (a wave
+// whose nodes are all walls or within the alpha = 2 short-cut skips the network).  Lanes past the end of a row
 // work on a clamped node and store nothing; walls and nodes at the near-equilibrium
 // short-cut feed zero features and keep their own result.
 template <class L, class St, int LAYOUT, bool FLAGS>
@@ -404,7 +399,10 @@ __global__ __launch_bounds__(512) void k_step_elbm_mlp(StepParams p) {
     const bool solve = active && !wall && dmax >= ALPHA_SHORTCUT;
 #pragma unroll
     for (int k = 0; k < MLP_IN; k++) xf[k] = solve ? xf[k] : 0.0f;
-    const double a0 = double(mlp_eval_wave(p.mlp_lane, p.mlp_wf, xf));  // all lanes of the wave
+    // the network runs for all lanes of the wave, and only in waves where some lane needs
+    // the solve (the condition is wave-uniform: a scalar branch, EXEC unchanged)
+    double a0 = 2.0;
+    if (__builtin_amdgcn_ballot_w64(solve) != 0) a0 = double(mlp_eval_wave(p.mlp_lane, p.mlp_wf, xf));
     // the moments for every lane (kept out of the divergent branch, where the compiler's
     // register allocation fails badly), the root where it is wanted
     alpha_moments<L, C>(h, heq, an);
@@ -420,6 +418,7 @@ __global__ __launch_bounds__(512) void k_step_elbm_mlp(StepParams p) {
 #pragma unroll
         for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
         conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
+        note_nonfinite<C>(p, o[0]);
 #pragma unroll
         for (int i = 0; i < Q; i++) out[i] = St::encode(o[i], C(L::w(i)), 0u);
         if (p.stats && active) {
@@ -544,6 +543,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
         conserve<L, C>(o, m[c].drho, m[c].jx + omega * (m[c].rho * ux - m[c].jx) + F[c][0],
                        m[c].jy + omega * (m[c].rho * uy - m[c].jy) + F[c][1],
                        m[c].jz + omega * (m[c].rho * uz - m[c].jz) + F[c][2]);
+        note_nonfinite<C>(p, o[0]);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             uint32_t rnd = 0;

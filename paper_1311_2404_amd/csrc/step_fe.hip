@@ -171,6 +171,7 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
         // g_0 = phi - sum_i g_i)
         h[0] = h[0] + ((drho - s0) - h[0]) * itr - s1;
         k[0] = k[0] + ((phi - sg) - k[0]) * itp;
+        note_nonfinite<C>(p, h[0] + k[0]);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             of[i] = St::encode(h[i], C(L::w(i)), 0u);

@@ -186,3 +186,18 @@ def test_free_energy_arguments(lbm):
         assert ei.value.code == lbm.LBM_EUNSUPPORTED
     finally:
         lbm.lbm_destroy(h)
+
+
+def test_pop_layout_setter_rejects_bad_arguments(lbm):
+    h = lbm.lbm_create(1, 0, 8, 8, 8, 0.7)
+    try:
+        for bad in (dict(kind=2), dict(tile_rows=3), dict(tile_rows=128), dict(tile_rows=-1), dict(row_pad=-1),
+                    dict(block_pad=-2), dict(soa_pad=1 << 21), dict(row_pad=(1 << 20) + 1)):
+            with pytest.raises(lbm.LbmError) as ei:
+                lbm.lbm_set_pop_layout(h, **bad)
+            assert ei.value.code == lbm.LBM_EINVAL, bad
+        for good in (dict(kind=lbm.LBM_POP_SOA, soa_pad=0), dict(tile_rows=1), dict(tile_rows=64, block_pad=-1),
+                     dict(row_pad=1 << 20)):
+            lbm.lbm_set_pop_layout(h, **good)
+    finally:
+        lbm.lbm_destroy(h)

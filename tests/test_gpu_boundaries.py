@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synthetic as S
-from test_gpu_parity import _LAYOUT_ENVS, _LAYOUT_KEYS, check_f64, gpu_run, oracle_run, rel
+from test_gpu_parity import _POP_LAYOUTS, check_f64, gpu_run, oracle_run, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -62,21 +62,15 @@ def test_cavity_aa_equals_ab_bitwise(storage):
         assert np.array_equal(fa, fb) and np.array_equal(ua, ub) and np.array_equal(ra, rb), (storage, steps)
 
 
-def test_cavity_population_layouts_agree_bitwise(monkeypatch):
+def test_cavity_population_layouts_agree_bitwise():
     c = cavity(S.D3Q19, S.SMAG, 37, 12, 6)
     for st in (P.LBM_F64, P.LBM_F32):
         for lay in (P.LBM_AB, P.LBM_AA):
             ref = gpu_run(c, 5, st, lay)
-            for env in _LAYOUT_ENVS:
-                for k in _LAYOUT_KEYS:
-                    monkeypatch.delenv(k, raising=False)
-                for k, v in env.items():
-                    monkeypatch.setenv(k, v)
-                got = gpu_run(c, 5, st, lay)
+            for pl in _POP_LAYOUTS:
+                got = gpu_run(c, 5, st, lay, pop_layout=pl)
                 for a, b in zip(got, ref):
-                    assert np.array_equal(a, b), (st, lay, env)
-            for k in _LAYOUT_KEYS:
-                monkeypatch.delenv(k, raising=False)
+                    assert np.array_equal(a, b), (st, lay, pl)
 
 
 def halfway_channel(lattice, model, nx, ny, nz, tau=0.6, force=(2e-5, 0.0, 0.0), seed=3):

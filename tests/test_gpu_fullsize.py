@@ -8,6 +8,8 @@ Navier-Stokes kinetic-energy law, conservation of mass and momentum, and the err
 each storage format against the FP64 run of the same kernel (itself matched to the
 oracle to 1e-12 in the parity tests).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -117,6 +119,43 @@ def test_c2_fullsize_1000_steps_decay_and_conservation():
     u_aa = s.macro()[1]
     s.close()
     assert np.array_equal(u_aa, runs[P.LBM_F32])
+
+
+C2_REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_taylor_green_256.npz")
+
+
+@pytest.mark.parametrize("storage,layout,tol", [(P.LBM_F64, P.LBM_AA, 1e-12), (P.LBM_F64, P.LBM_AB, 1e-12),
+                                                (P.LBM_F32, P.LBM_AA, 1e-5), (P.LBM_F32S, P.LBM_AA, 1e-5)])
+def test_c2_fullsize_1000_steps_vs_oracle(storage, layout, tol):
+    """The metric's configuration itself, 256^3 for its 1000 steps, against the FP64
+    oracle's own run of it (stored by tests/golden/make_c2_reference.py, which calls
+    only the oracle): the velocity at 8192 sampled nodes, and over the whole lattice the
+    per-plane sums of |u|^2 and of (rho - 1)^2 and the kinetic energy.  FP64 storage:
+    1e-12 relative on velocity (and density); FP32 compute: 1e-5 on velocity."""
+    ref = np.load(C2_REF)
+    c = c2_case()
+    s = P.Sim.from_case(c, storage, layout)
+    s.step(int(ref["steps"]))
+    rho, u = s.macro()
+    s.close()
+    n = int(ref["n"])
+    nodes = ref["nodes"]
+    err_u = rel(u[:, nodes], ref["u"])
+    pu2 = (u.reshape(3, n, n * n) ** 2).sum(axis=2).sum(axis=0)
+    err_plane = float(np.abs(pu2 / ref["plane_u2"].sum(axis=0) - 1.0).max())
+    ke = 0.5 * float((u * u).sum()) / n ** 3
+    print("%s layout %d: sampled velocity %.2e, per-plane |u|^2 %.2e, KE %.2e" % (
+        P.STORAGE_NAMES[storage], layout, err_u, err_plane, abs(ke / ref["ke"][1] - 1)))
+    assert err_u <= tol
+    # |u|^2 is quadratic in u: a relative velocity error e moves it by at most ~2e
+    assert err_plane <= 2 * tol
+    assert abs(ke / ref["ke"][1] - 1.0) <= 2 * tol
+    if storage == P.LBM_F64:
+        # rho - 1 ~ 1e-3 (the vortex's pressure); floor of 1e-15 of rho per node
+        dr = rho[0, nodes] - ref["rho"]
+        assert np.linalg.norm(dr) <= tol * np.linalg.norm(ref["rho"] - 1) + 1e-15 * np.linalg.norm(ref["rho"])
+        pr2 = ((rho[0].reshape(n, n * n) - 1.0) ** 2).sum(axis=1)
+        assert np.abs(pr2 / ref["plane_drho2"] - 1.0).max() <= 2 * tol + 1e-12
 
 
 # ----------------------------------------------------------- C3: D3Q19 MRT duct 128x128x512

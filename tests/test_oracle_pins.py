@@ -604,6 +604,41 @@ def test_mlp_series_base_is_the_newton_series():
         assert abs(a_ser[0] - a_mlp[0]) <= 1e-12
 
 
+def _feature_state(lattice, eps, scale):
+    """Populations f = scale * w and a comparison state feq = f (1 + d) with d = +2 eps on
+    every axis link, -eps on every diagonal link and 0 at rest, so that d_i = (feq_i - f_i)/f_i
+    and the moments a_k = sum_i f_i d_i^k follow by hand from the weight table: the axis
+    links carry weight 1/3 and the diagonal links 1/3 on D3Q19 (6 x 1/18, 12 x 1/36), 4/9 and
+    1/9 on D2Q9 (4 x 1/9, 4 x 1/36), so a_k = scale (W_ax (2 eps)^k + W_dg (-eps)^k)."""
+    e, w, _ = oracle.tables(lattice)
+    nrm = np.abs(e).sum(axis=1)
+    d = np.where(nrm == 1, 2 * eps, np.where(nrm == 2, -eps, 0.0))
+    f = scale * w
+    return f, f * (1 + d)
+
+
+@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
+def test_alpha_features_closed_form(lattice):
+    """The six network inputs on hand-built states whose moments are known in closed
+    form: log10(a2/rho), a3/a2, a4/a2, max(-d), max(d) and |v|^2/c_s^2 = 3 |v|^2.  The
+    numbers are chosen so that a natural logarithm for log10, a missing 1/c_s^2, moments
+    weighted by w instead of f or a swapped sign of d each move a feature far outside the
+    tolerance."""
+    w_ax, w_dg = (Fraction(1, 3), Fraction(1, 3)) if lattice == S.D3Q19 else (Fraction(4, 9), Fraction(1, 9))
+    for eps, scale, rho, vsq in ((0.01, 1.0, 1.0, 0.0012), (0.003, 2.0, 1.7, 0.0), (0.05, 0.5, 0.8, 0.01)):
+        f, feq = _feature_state(lattice, eps, scale)
+        feat = oracle.alpha_features(lattice, f, feq, rho, vsq)
+        a2 = scale * float(w_ax * 4 + w_dg) * eps ** 2
+        a3 = scale * float(w_ax * 8 - w_dg) * eps ** 3
+        a4 = scale * float(w_ax * 16 + w_dg) * eps ** 4
+        want = [np.log(a2 / rho) / np.log(10.0), a3 / a2, a4 / a2, eps, 2 * eps, vsq / (1.0 / 3.0)]
+        np.testing.assert_allclose(feat, want, rtol=1e-12, atol=1e-15)
+    # a state with a2 = 1e-4 rho: log10 gives exactly -4 (ln would give -9.21)
+    eps = np.sqrt(1e-4 / float(w_ax * 4 + w_dg))
+    f, feq = _feature_state(lattice, eps, 1.0)
+    assert abs(oracle.alpha_features(lattice, f, feq, 1.0, 0.0)[0] - (-4.0)) <= 1e-12
+
+
 def test_init_is_equilibrium_plus_perturbation():
     c = S.c2_taylor_green(n=6, noise=1e-6)
     o = oracle.Oracle.from_case(c)
