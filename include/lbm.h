@@ -93,7 +93,11 @@ int lbm_create(int lattice, int model, int nx, int ny, int nz, double tau,
 
 /* Storage (LBM_F64 ... LBM_F16S) and layout (LBM_AB, LBM_AA); stochastic_round != 0
  * rounds BF16/F16 stores stochastically (counter-hash seeded, unbiased) instead of to
- * nearest even.  Only before the first init; default LBM_F32, LBM_AB, round to nearest. */
+ * nearest even (LBGK, MRT, regularized and Smagorinsky only: LBM_EUNSUPPORTED for the
+ * other models).  The Shan-Chen and free-energy models keep F64, F32 or shifted F32
+ * populations (LBM_EUNSUPPORTED): their component densities leave 1 by O(1), where the
+ * 16-bit rounding of f - w no longer conserves mass.  Only before the first init;
+ * default LBM_F32, LBM_AB, round to nearest. */
 int lbm_set_storage(lbm_sim *sim, int storage, int layout, int stochastic_round);
 
 /* Population layout in HBM.  Only before the first init; the results do not depend on

@@ -43,6 +43,18 @@ hipError_t with_storage(int storage, int sr, F &&f) {
     }
 }
 
+// The 4- and 8-byte storages only: the two-component models (Shan-Chen, free energy),
+// whose densities leave 1 by O(1), keep no 16-bit populations.
+template <class F>
+hipError_t with_wide_storage(int storage, F &&f) {
+    switch (storage) {
+    case ST_F64: return f(StF64{});
+    case ST_F32: return f(StF32{});
+    case ST_F32S: return f(StF32S{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <class F>
 hipError_t with_layout(int layout, F &&f) {
     switch (layout) {

@@ -385,19 +385,4 @@ __device__ __forceinline__ AlphaOut alpha_root(const C *h, const C *heq, const A
     return alpha_newton_log<L, C>(h, heq, s, a0, tol, maxit);
 }
 
-// Full alpha for one node from its shifted populations h and shifted entropic
-// equilibrium heq: short-cut near equilibrium, first guess (2 or the series estimate),
-// then the FP64 root.  (The MLP first guess has a kernel of its own, k_step_elbm_mlp.)
-template <class L, class C>
-__device__ __forceinline__ AlphaOut alpha_solve(const C *h, const C *heq, const StepParams &p) {
-    AlphaNode s;
-    alpha_prepare<L, C>(h, heq, s);
-    if (s.dmax < ALPHA_SHORTCUT) return {2.0, 0, 1};
-    double a0 = 2.0;
-    if (p.alpha_init == 1) {
-        a0 = 2.0 + (s.am[3] - 2.0 * s.am[4]) / (3.0 * s.am[2]);
-    }
-    return alpha_root<L, C>(h, heq, s, a0, p.alpha_tol, p.alpha_maxit);
-}
-
 }  // namespace lbm

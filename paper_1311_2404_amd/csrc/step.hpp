@@ -66,10 +66,14 @@ namespace lbm {
 // raises *p.diverged, which the next synchronising call of the library reads back.  The
 // rest population is formed from the node's mass (the conservation restore, or the
 // free-energy rest equation), so a non-finite population or moment anywhere in the node
-// reaches it: one class test per node.
+// reaches it: one class test per node, and the rarely taken store at the kernel's end,
+// after the population stores.
 template <class C>
-__device__ __forceinline__ void note_nonfinite(const StepParams &p, C v) {
-    if (!__builtin_isfinite(v)) *p.diverged = 1u;
+__device__ __forceinline__ bool nonfinite(C v) {
+    return !__builtin_isfinite(v);
+}
+__device__ __forceinline__ void raise_divergence(const StepParams &p, bool bad) {
+    if (bad) *p.diverged = 1u;
 }
 
 // A node and its periodic neighbours.  at() is the linear node index (flags, psi,
@@ -240,18 +244,6 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     if constexpr (MULTI_ROW) y = blockIdx.y * blockDim.y + __builtin_amdgcn_readfirstlane(threadIdx.y);
     else y = blockIdx.y;
     const int z = blockIdx.z;
-    const int tid = MULTI_ROW ? threadIdx.y * blockDim.x + threadIdx.x : threadIdx.x;
-    const int nthr = MULTI_ROW ? blockDim.x * blockDim.y : blockDim.x;
-
-    // ELBM only: the Newton-iteration histogram in LDS
-    constexpr bool ELBM = MODEL == M_ELBM;
-    __shared__ uint32_t s_hist[ELBM ? NEWTON_BINS + 1 : 1];
-    if constexpr (ELBM) {
-        if (p.stats) {
-            for (int k = tid; k < NEWTON_BINS + 1; k += nthr) s_hist[k] = 0u;
-            __syncthreads();
-        }
-    }
 
     // AB steps on padded rows (row-interleaved layout): lanes past the row's end run the
     // step on the row's last node and store the result into the row's padding, which is
@@ -277,9 +269,10 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             raw[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
         }
         T out[Q];
+        bool bad = false;
         const uint32_t fl = FLAGS ? p.flags[n] : 0u;
         // equilibrium velocity nodes exist for the polynomial-equilibrium models
-        const bool vel = FLAGS == 2 && MODEL != M_ELBM && fl == 2u;
+        const bool vel = FLAGS == 2 && fl == 2u;
         if (fl == 1u) {
             // full-way bounce-back: the stored values are returned along -e_i untouched
 #pragma unroll
@@ -288,7 +281,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             C h[Q], o[Q];
 #pragma unroll
             for (int i = 0; i < Q; i++) h[i] = St::decode(raw[i], C(L::w(i)));
-            if (FLAGS == 2 && MODEL != M_ELBM && fl == 3u) complete_missing<L, C>(h, p, g);
+            if (FLAGS == 2 && fl == 3u) complete_missing<L, C>(h, p, g);
             if (vel) {
                 velocity_node<L, C>(h, o, p, g);
             } else if constexpr (MODEL == M_BGK) {
@@ -297,38 +290,15 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                 collide_mrt<L, C>(h, o, p);
             } else if constexpr (MODEL == M_REG) {
                 collide_reg<L, C>(h, o, p);
-            } else if constexpr (MODEL == M_SMAG) {
-                collide_smag<L, C>(h, o, p);
             } else {
-                const Macro<C> m = moments<L, C>(h);
-                const C irho = C(1) / m.rho;
-                const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
-                C heq[Q];
-                entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
-                const AlphaOut ao = alpha_solve<L, C>(h, heq, p);
-                const C ab = C(ao.alpha * p.beta);
-#pragma unroll
-                for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
-                conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
-                if (p.stats && active) {
-                    atomicAdd(&s_hist[ao.iters < NEWTON_BINS ? ao.iters : NEWTON_BINS - 1], 1u);
-                    if (!ao.converged) atomicAdd(&s_hist[NEWTON_BINS], 1u);
-                }
+                static_assert(MODEL == M_SMAG, "k_step: LBGK, MRT, regularized or Smagorinsky collision");
+                collide_smag<L, C>(h, o, p);
             }
-            note_nonfinite<C>(p, o[0]);
-            // stochastic rounding reads the top 16 bits of rnd: one draw serves two values
-            SrStream rs{0u};
-            uint32_t draw = 0;
-            if constexpr (St::stochastic) rs = sr_stream(n, hash32(p.seed ^ hash32(p.step + 0x9e3779b9u)));
+            bad = nonfinite<C>(o[0]);
+            uint32_t r0 = 0;
+            if constexpr (St::stochastic) r0 = sr_word0(n, hash32(p.seed ^ hash32(p.step + 0x9e3779b9u)));
 #pragma unroll
-            for (int i = 0; i < Q; i++) {
-                uint32_t rnd = 0;
-                if constexpr (St::stochastic) {
-                    if (i % 2 == 0) draw = rs.next();
-                    rnd = i % 2 == 0 ? draw : draw << 16;
-                }
-                out[i] = St::encode(o[i], C(L::w(i)), rnd);
-            }
+            for (int i = 0; i < Q; i++) out[i] = St::encode(o[i], C(L::w(i)), St::stochastic ? sr_word(r0, i) : 0u);
         }
 #pragma unroll
         for (int i = 0; i < Q; i++) {
@@ -337,37 +307,87 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
             if constexpr (LAYOUT == LAYOUT_AB) LBM_STORE(pop_addr(dst, S, slot, gs, 0, 0, 0), out[i]);
             else LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), out[i], i);
         }
-    }
-    if constexpr (ELBM) {
-        if (p.stats) {
-            __syncthreads();
-            for (int k = tid; k < NEWTON_BINS + 1; k += nthr)
-                if (s_hist[k]) atomicAdd(&p.stats[k], (unsigned long long)s_hist[k]);
-        }
+        raise_divergence(p, bad);
     }
 }
 
-// The entropic step with the MLP first guess.  The network runs on the matrix cores for
-// the 64 nodes of a wave at once (mlp_eval_wave), which needs every lane of the wave at
-// that point: so this kernel does not branch around it per lane, only per wave (a wave
-// whose nodes are all walls or within the alpha = 2 short-cut skips the network).  Lanes past the end of a row
-// work on a clamped node and store nothing; walls and nodes at the near-equilibrium
-// short-cut feed zero features and keep their own result.
-template <class L, class St, int LAYOUT, bool FLAGS>
-__global__ __launch_bounds__(512) void k_step_elbm_mlp(StepParams p) {
+// Nodes whose alpha needs the logarithmic form (max |d_i| > ALPHA_SERIES_DMAX) are few
+// but spread: at step 8000 of the 256^3 entropic vortex 9% of the nodes, so nearly every
+// wave has some, and a divergent branch would run every wave through the logarithms for
+// a few lanes.  Such nodes are queued in LDS instead (f_i, d_i, the first guess and a_max
+// of each) and the workgroup's first wave solves them with its lanes packed, log1p(d_i)
+// included; each queued node then reads its alpha back.  A queue entry takes 472 bytes;
+// nodes beyond the capacity solve in place.
+constexpr int ALPHA_LOGQ = 64;
+
+template <int Q>
+struct AlphaLogQueue {
+    double f[Q][ALPHA_LOGQ], d[Q][ALPHA_LOGQ], l1[Q][ALPHA_LOGQ];
+    double a0[ALPHA_LOGQ], amax[ALPHA_LOGQ], alpha[ALPHA_LOGQ];
+    int iters[ALPHA_LOGQ], conv[ALPHA_LOGQ];
+    int count;
+};
+
+// Newton with bisection safeguard on the logarithmic form of g for queue entry e: the
+// iteration of alpha_newton_log, with log1p(d_i) taken once per node instead of once per
+// iteration.
+template <int Q>
+__device__ __forceinline__ void alpha_newton_log_queued(AlphaLogQueue<Q> &sq, int e, double tol, int maxit) {
+#pragma unroll 1
+    for (int i = 0; i < Q; i++) sq.l1[i][e] = log1p(sq.d[i][e]);
+    double lo = 1.0, hi = sq.amax[e], a = sq.a0[e];
+    if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
+    for (int k = 1; k <= maxit; k++) {
+        double g = 0.0, dg = 0.0, gs = 0.0;
+#pragma unroll 1
+        for (int i = 0; i < Q; i++) {
+            const double f = sq.f[i][e], d = sq.d[i][e], l1 = sq.l1[i][e];
+            const double ad = a * d;
+            const double la = log1p(ad);
+            const double t1 = f * (1.0 + ad) * la, t2 = f * ad * l1;
+            g += t1 - t2;
+            dg += f * d * (la - l1);
+            gs += fabs(t1) + fabs(t2);
+        }
+        if (fabs(g) <= 64.0 * 2.220446049250313e-16 * gs) {
+            sq.alpha[e] = a, sq.iters[e] = k, sq.conv[e] = 1;
+            return;
+        }
+        if (g < 0.0) lo = a; else hi = a;
+        double an = a - g / dg;
+        if (fabs(an - a) <= tol) {
+            sq.alpha[e] = an, sq.iters[e] = k, sq.conv[e] = 1;
+            return;
+        }
+        if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
+        a = an;
+    }
+    sq.alpha[e] = fmin(2.0, 0.99 * sq.amax[e]), sq.iters[e] = maxit, sq.conv[e] = 0;
+}
+
+// The entropic step.  One x row (segment) per workgroup; every lane of the workgroup runs
+// the whole kernel (lanes past the row's end on a clamped node, storing nothing; wall
+// nodes and nodes at the alpha = 2 short-cut keep their own result), because the MLP
+// first guess runs on the matrix cores for the 64 nodes of a wave at once and the
+// logarithmic fallback is shared through LDS.  MLP: alpha_init = 2 (the network's guess,
+// skipped in waves where no lane needs a solve); otherwise alpha_init 0 (alpha0 = 2) or
+// 1 (the series estimate).
+template <class L, class St, int LAYOUT, bool FLAGS, bool MLP>
+__global__ __launch_bounds__(512) void k_step_elbm(StepParams p) {
     using T = typename St::T;
     using C = typename St::C;
     constexpr int Q = L::Q;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;  // one x row (segment) per workgroup
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const int z = blockIdx.z;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     __shared__ uint32_t s_hist[NEWTON_BINS + 1];
-    if (p.stats) {
+    __shared__ AlphaLogQueue<Q> sq;
+    if (tid == 0) sq.count = 0;
+    if (p.stats)
         for (int k = tid; k < NEWTON_BINS + 1; k += nthr) s_hist[k] = 0u;
-        __syncthreads();
-    }
+    __syncthreads();
     const bool active = x < p.nx;
     const Geo g = make_geo(active ? x : p.nx - 1, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     const uint32_t n = g.at(0, 0, 0);
@@ -390,25 +410,55 @@ __global__ __launch_bounds__(512) void k_step_elbm_mlp(StepParams p) {
     const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
     C heq[Q];
     entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
-    const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
-    // the features first, so that the 16 moments are not live across the network
     AlphaNode an;
     alpha_project<L, C>(h, heq, an);
-    float xf[MLP_IN];
-    const double dmax = alpha_feature_pass<L, C>(h, heq, an, double(m.rho), vsq, xf);
-    const bool solve = active && !wall && dmax >= ALPHA_SHORTCUT;
-#pragma unroll
-    for (int k = 0; k < MLP_IN; k++) xf[k] = solve ? xf[k] : 0.0f;
-    // the network runs for all lanes of the wave, and only in waves where some lane needs
-    // the solve (the condition is wave-uniform: a scalar branch, EXEC unchanged)
     double a0 = 2.0;
-    if (__builtin_amdgcn_ballot_w64(solve) != 0) a0 = double(mlp_eval_wave(p.mlp_lane, p.mlp_wf, xf));
-    // the moments for every lane (kept out of the divergent branch, where the compiler's
-    // register allocation fails badly), the root where it is wanted
+    if constexpr (MLP) {
+        // the features first, so that the moments are not live across the network
+        const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
+        float xf[MLP_IN];
+        const double dmax = alpha_feature_pass<L, C>(h, heq, an, double(m.rho), vsq, xf);
+        const bool want = active && !wall && dmax >= ALPHA_SHORTCUT;
+#pragma unroll
+        for (int k = 0; k < MLP_IN; k++) xf[k] = want ? xf[k] : 0.0f;
+        // all lanes of the wave, and only in waves where some lane needs the solve (the
+        // condition is wave-uniform: a scalar branch, EXEC unchanged)
+        if (__builtin_amdgcn_ballot_w64(want) != 0) a0 = double(mlp_eval_wave(p.mlp_lane, p.mlp_wf, xf));
+    }
     alpha_moments<L, C>(h, heq, an);
+    const bool solve = active && !wall && an.dmax >= ALPHA_SHORTCUT;
+    if constexpr (!MLP) {
+        if (p.alpha_init == 1) a0 = 2.0 + (an.am[3] - 2.0 * an.am[4]) / (3.0 * an.am[2]);
+    }
     AlphaOut ao{2.0, 0, 1};
-    if (solve) ao = alpha_root<L, C>(h, heq, an, a0, p.alpha_tol, p.alpha_maxit);
+    const bool logf = solve && an.dmax > ALPHA_SERIES_DMAX;
+    if (solve && !logf) {
+        if (an.khi) ao = alpha_newton_moments<ALPHA_K>(an.am, a0, 2.5, p.alpha_tol, p.alpha_maxit);
+        else ao = alpha_newton_moments<ALPHA_K_LO>(an.am, a0, 2.5, p.alpha_tol, p.alpha_maxit);
+    }
+    int qslot = -1;
+    if (logf) {
+        qslot = atomicAdd(&sq.count, 1);
+        if (qslot < ALPHA_LOGQ) {
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const double f = L::w(i) + double(h[i]);
+                sq.f[i][qslot] = f;
+                sq.d[i][qslot] = alpha_D<L, C>(h, heq, an, i) * recip<C>(f);
+            }
+            sq.a0[qslot] = a0;
+            sq.amax[qslot] = an.amax;
+        } else {
+            ao = alpha_newton_log<L, C>(h, heq, an, a0, p.alpha_tol, p.alpha_maxit);
+        }
+    }
+    __syncthreads();
+    const int nq = min(sq.count, ALPHA_LOGQ);
+    for (int e = tid; e < nq; e += nthr) alpha_newton_log_queued<Q>(sq, e, p.alpha_tol, p.alpha_maxit);
+    __syncthreads();
+    if (qslot >= 0 && qslot < ALPHA_LOGQ) ao = AlphaOut{sq.alpha[qslot], sq.iters[qslot], sq.conv[qslot]};
     T out[Q];
+    bool bad = false;
     if (wall) {
 #pragma unroll
         for (int i = 0; i < Q; i++) out[i] = raw[opp(i)];
@@ -418,7 +468,7 @@ __global__ __launch_bounds__(512) void k_step_elbm_mlp(StepParams p) {
 #pragma unroll
         for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
         conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
-        note_nonfinite<C>(p, o[0]);
+        bad = nonfinite<C>(o[0]);
 #pragma unroll
         for (int i = 0; i < Q; i++) out[i] = St::encode(o[i], C(L::w(i)), 0u);
         if (p.stats && active) {
@@ -433,6 +483,7 @@ __global__ __launch_bounds__(512) void k_step_elbm_mlp(StepParams p) {
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
             LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), out[i], i);
         }
+        raise_divergence(p, bad);
     }
     if (p.stats) {
         __syncthreads();
@@ -522,7 +573,7 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
     const C ux = (m[0].jx + m[1].jx) * irs, uy = (m[0].jy + m[1].jy) * irs, uz = (m[0].jz + m[1].jz) * irs;
     const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
     const C omega = C(p.omega);
-    const uint32_t key = sizeof(T) == 2 ? hash32(p.seed ^ hash32(p.step + 0x9e3779b9u)) : 0u;
+    bool bad = false;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
         const C ir = C(1) / m[c].rho;
@@ -543,16 +594,15 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
         conserve<L, C>(o, m[c].drho, m[c].jx + omega * (m[c].rho * ux - m[c].jx) + F[c][0],
                        m[c].jy + omega * (m[c].rho * uy - m[c].jy) + F[c][1],
                        m[c].jz + omega * (m[c].rho * uz - m[c].jz) + F[c][2]);
-        note_nonfinite<C>(p, o[0]);
+        bad = bad || nonfinite<C>(o[0]);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            uint32_t rnd = 0;
-            if constexpr (sizeof(T) == 2) rnd = hash32(((n * 19u + uint32_t(i)) * 2u + uint32_t(c)) ^ key);
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            LBM_STORE_POP(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), rnd), i);
+            LBM_STORE_POP(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), 0u), i);
         }
     }
+    raise_divergence(p, bad);
 }
 
 // Launches k_step<MODEL> for every lattice, storage (with the stochastic-rounding

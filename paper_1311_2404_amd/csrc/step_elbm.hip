@@ -12,12 +12,13 @@ hipError_t launch_step_elbm(int lattice, int storage, int layout, int flags, con
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
-                if (p.alpha_init == 2 && p.mlp) {
-                    if (flags) k_step_elbm_mlp<L, St, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
-                    else k_step_elbm_mlp<L, St, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                const bool mlp = p.alpha_init == 2 && p.mlp;
+                if (mlp) {
+                    if (flags) k_step_elbm<L, St, LAY, true, true><<<c.grid, c.block, 0, c.stream>>>(p);
+                    else k_step_elbm<L, St, LAY, false, true><<<c.grid, c.block, 0, c.stream>>>(p);
                 } else {
-                    if (flags) k_step<L, St, M_ELBM, LAY, 1><<<c.grid, c.block, 0, c.stream>>>(p);
-                    else k_step<L, St, M_ELBM, LAY, 0><<<c.grid, c.block, 0, c.stream>>>(p);
+                    if (flags) k_step_elbm<L, St, LAY, true, false><<<c.grid, c.block, 0, c.stream>>>(p);
+                    else k_step_elbm<L, St, LAY, false, false><<<c.grid, c.block, 0, c.stream>>>(p);
                 }
                 return hipGetLastError();
             });

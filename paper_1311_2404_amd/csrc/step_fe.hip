@@ -91,6 +91,7 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
     }
     const uint32_t fl = FLAGS ? p.flags[n] : 0u;
     T of[Q], og[Q];
+    bool bad = false;
     if (fl == 1u) {
         // full-way bounce-back on both lattices
 #pragma unroll
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
         // g_0 = phi - sum_i g_i)
         h[0] = h[0] + ((drho - s0) - h[0]) * itr - s1;
         k[0] = k[0] + ((phi - sg) - k[0]) * itp;
-        note_nonfinite<C>(p, h[0] + k[0]);
+        bad = nonfinite<C>(h[0] + k[0]);
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             of[i] = St::encode(h[i], C(L::w(i)), 0u);
@@ -185,16 +186,7 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
         LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), of[i], i);
         LBM_STORE_POP(pop_addr(dst, S, Q + slot, g, dx, dy, dz), og[i], i);
     }
-}
-
-template <class F>
-hipError_t with_fe_storage(int storage, F &&fn) {
-    switch (storage) {
-    case ST_F64: return fn(StF64{});
-    case ST_F32: return fn(StF32{});
-    case ST_F32S: return fn(StF32S{});
-    default: return hipErrorInvalidValue;
-    }
+    raise_divergence(p, bad);
 }
 
 }  // namespace
@@ -202,7 +194,7 @@ hipError_t with_fe_storage(int storage, F &&fn) {
 hipError_t launch_fe_phi(int lattice, int storage, int layout, bool flags, const StepParams &p, const LaunchCfg &c) {
     return with_lattice(lattice, [&](auto lt) {
         using L = decltype(lt);
-        return with_fe_storage(storage, [&](auto st) {
+        return with_wide_storage(storage, [&](auto st) {
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
@@ -218,7 +210,7 @@ hipError_t launch_step_fe(int lattice, int storage, int layout, bool flags, cons
                           const LaunchCfg &c) {
     return with_lattice(lattice, [&](auto lt) {
         using L = decltype(lt);
-        return with_fe_storage(storage, [&](auto st) {
+        return with_wide_storage(storage, [&](auto st) {
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;

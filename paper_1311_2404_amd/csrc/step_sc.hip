@@ -7,7 +7,7 @@ namespace lbm {
 hipError_t launch_psi(int lattice, int storage, int layout, const StepParams &p, const LaunchCfg &c) {
     return with_lattice(lattice, [&](auto lt) {
         using L = decltype(lt);
-        return with_storage<false>(storage, 0, [&](auto st) {
+        return with_wide_storage(storage, [&](auto st) {
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
@@ -21,7 +21,7 @@ hipError_t launch_psi(int lattice, int storage, int layout, const StepParams &p,
 hipError_t launch_step_sc(int lattice, int storage, int layout, const StepParams &p, const LaunchCfg &c) {
     return with_lattice(lattice, [&](auto lt) {
         using L = decltype(lt);
-        return with_storage<false>(storage, 0, [&](auto st) {
+        return with_wide_storage(storage, [&](auto st) {
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;

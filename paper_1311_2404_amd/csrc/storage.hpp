@@ -30,21 +30,23 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
     return x;
 }
 
-// Random bits for stochastic rounding: one hash per node and step seeds Marsaglia's
-// xorshift32 (shifts 13, 17, 5); each step gives the random bits of two stored values
-// (its high and its low half).  The seed is forced odd so the state is never 0.
-struct SrStream {
-    uint32_t s;
-    __device__ __forceinline__ uint32_t next() {
-        s ^= s << 13;
-        s ^= s >> 17;
-        s ^= s << 5;
-        return s;
-    }
-};
-__device__ __forceinline__ SrStream sr_stream(uint32_t node, uint32_t step_key) {
-    return SrStream{hash32(node ^ step_key) | 1u};
-}
+// Random words for stochastic rounding: one hash per node and step, r0, and for the
+// stored value i the Weyl sequence r0 + i * 0x9e3779b9 (the golden-ratio increment; one
+// add per value).  Each word is uniform over nodes and steps, which is what makes the
+// rounding of every value unbiased; the words of one node are spread evenly over
+// [0, 2^32) instead of being independent, which only lowers the variance of sums over
+// the node's populations.
+__device__ __forceinline__ uint32_t sr_word0(uint32_t node, uint32_t step_key) { return hash32(node ^ step_key); }
+__device__ __forceinline__ uint32_t sr_word(uint32_t r0, int i) { return r0 + uint32_t(i) * 0x9e3779b9u; }
+
+// gfx950's stochastic-rounding converts (v_cvt_sr_bf16_f32, v_cvt_sr_f16_f32) round an
+// FP32 value up with probability equal to the dropped fraction of an ulp, taking the
+// random word as a fraction in [0, 1) from its top bits (an in-bounds probe on the GPU:
+// with the dropped fraction exactly 1/2, the word 2^31 rounds up and 2^31 - 1 does not;
+// over 65 536 words the mean lands on the value within the sampling noise, for normal
+// and subnormal BF16 and F16 results and both signs).
+typedef __bf16 sr_bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 sr_f16x2 __attribute__((ext_vector_type(2)));
 
 struct StF64 {
     using T = double;  // element in memory
@@ -76,9 +78,8 @@ struct StF32S {
     __device__ static __forceinline__ T encode(C h, C, uint32_t) { return h; }
 };
 
-// bfloat16 kept as raw bits: decode is a 16-bit shift, encode rounds to nearest even
-// (hardware convert) or stochastically (add 16 random bits below the kept mantissa,
-// then truncate; unbiased for finite values).
+// bfloat16 kept as raw bits: decode is a 16-bit shift, encode rounds to nearest even or
+// stochastically (hardware converts of both kinds).
 template <bool SR>
 struct StBF16S {
     using T = uint16_t;
@@ -89,8 +90,9 @@ struct StBF16S {
     __device__ static __forceinline__ C decode(T v, C) { return __uint_as_float(uint32_t(v) << 16); }
     __device__ static __forceinline__ T encode(C h, C, uint32_t rnd) {
         if constexpr (SR) {
-            uint32_t b = __float_as_uint(h);
-            return uint16_t((b + (rnd >> 16)) >> 16);
+            sr_bf16x2 v = {};
+            v = __builtin_amdgcn_cvt_sr_bf16_f32(v, h, rnd, false);
+            return __builtin_bit_cast(uint16_t, v[0]);
         } else {
             __bf16 r = static_cast<__bf16>(h);
             return __builtin_bit_cast(uint16_t, r);
@@ -98,14 +100,8 @@ struct StBF16S {
     }
 };
 
-// IEEE half kept as raw bits.  Stochastic rounding rounds |h| up to the next half with
-// probability equal to the fraction of a half-ulp step it lies above the one below:
-//  - F16 normal range (|h| >= 2^-14): the half keeps 10 of FP32's 23 mantissa bits, so
-//    13 random bits are added below the kept ones and the rest truncated; a carry
-//    moves into the exponent as it should;
-//  - subnormal range: the spacing is 2^-24, so floor(|h| 2^24 + u) 2^-24, u from the
-//    top 16 random bits.
-// Either result is a half exactly, so the final conversion does not round.
+// IEEE half kept as raw bits; encode rounds to nearest even or stochastically (the
+// hardware converts; subnormal halves included).
 template <bool SR>
 struct StF16S {
     using T = uint16_t;
@@ -118,11 +114,9 @@ struct StF16S {
     }
     __device__ static __forceinline__ T encode(C h, C, uint32_t rnd) {
         if constexpr (SR) {
-            const float a = fabsf(h);
-            const float up = __uint_as_float((__float_as_uint(a) + (rnd >> 19)) & ~0x1fffu);
-            const float sub = floorf(fmaf(a, 0x1p24f, float(rnd >> 16) * 0x1p-16f)) * 0x1p-24f;
-            const float q = a >= 0x1p-14f ? up : sub;
-            return __builtin_bit_cast(uint16_t, static_cast<_Float16>(copysignf(q, h)));
+            sr_f16x2 v = {};
+            v = __builtin_amdgcn_cvt_sr_f16_f32(v, h, rnd, false);
+            return __builtin_bit_cast(uint16_t, v[0]);
         } else {
             return __builtin_bit_cast(uint16_t, static_cast<_Float16>(h));
         }

@@ -201,3 +201,16 @@ def test_pop_layout_setter_rejects_bad_arguments(lbm):
             lbm.lbm_set_pop_layout(h, **good)
     finally:
         lbm.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("model", [3, 6])  # Shan-Chen, free energy
+@pytest.mark.parametrize("storage", [3, 4])  # BF16S, F16S
+def test_two_component_models_refuse_16_bit_storage(lbm, model, storage):
+    h = lbm.lbm_create(1, model, 8, 8, 8, 0.9)
+    try:
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_set_storage(h, storage, lbm.LBM_AB, 0)
+        assert ei.value.code == lbm.LBM_EUNSUPPORTED
+        lbm.lbm_set_storage(h, lbm.LBM_F32S, lbm.LBM_AA, 0)
+    finally:
+        lbm.lbm_destroy(h)

