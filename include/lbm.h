@@ -203,6 +203,19 @@ int lbm_macro_device(lbm_sim *sim, void *rho_dev, void *u_dev, int fp64);
  * nodes with non-finite or non-positive density.  Synchronises. */
 int lbm_diag(lbm_sim *sim, double out[8]);
 
+/* lbm_diag without allocating: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation).  The
+ * same eight sums as lbm_diag (out[7] = 0), taken straight from the populations by a
+ * fused reduction (no FP64 field pass, so the sums agree with lbm_diag's to rounding
+ * order, ~1e-15 relative), written into the caller's device buffer out_dev (8 doubles,
+ * FP64) and enqueued on the handle's stream without synchronising.  No device memory is
+ * allocated or freed: the partial sums live in a static device array of 2048 x 8 doubles
+ * (131 KB per GPU, held until the process ends) that every call on that GPU shares and
+ * fully overwrites, so any lattice fits and nothing needs clearing; calls that overlap on
+ * one GPU (several handles on different streams) race on it.  The state must exist
+ * (LBM_ESTATE otherwise). */
+int lbm_diag_noalloc(lbm_sim *sim, void *out_dev);
+
 /* ELBM Newton statistics since the last reset: hist[k] = node updates that took k
  * Newton iterations (k = 0: alpha = 2 short-cut), k < nbins <= 32; *nonconv = updates
  * without convergence.  enable != 0 turns collection on (it costs an LDS histogram per

@@ -50,6 +50,7 @@ _SIGS = [
     ("lbm_macro", C.c_int, [_vp, _dp, _dp]),
     ("lbm_macro_device", C.c_int, [_vp, _vp, _vp, C.c_int]),
     ("lbm_diag", C.c_int, [_vp, _dp]),
+    ("lbm_diag_noalloc", C.c_int, [_vp, _vp]),
     ("lbm_elbm_stats", C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(_i64), C.c_int, C.POINTER(_i64)]),
     ("lbm_mlp_set_weights", C.c_int, [_vp, _fp, C.c_int]),
     ("lbm_mlp_get_weights", C.c_int, [_vp, _fp, C.c_int]),
@@ -215,6 +216,12 @@ def lbm_diag(sim):
     out = np.zeros(8)
     _err(sim, lib().lbm_diag(sim, _d(out)))
     return out
+
+
+def lbm_diag_noalloc(sim, out_t):
+    """The diagnostics into a CUDA float64 tensor of 8 elements (enqueued, no sync)."""
+    import torch
+    _err(sim, lib().lbm_diag_noalloc(sim, _ptr(out_t, 8, torch.float64)))
 
 
 def lbm_elbm_stats(sim, enable=True, reset=False, nbins=32):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +74,9 @@ struct lbm_sim {
     uint32_t seed = 0x2013b1u;
     std::string err;
 };
+
+constexpr int DIAG_SCRATCH_BLOCKS = 2048;  // partial-sum sets of lbm_diag_noalloc's reduction
+static __device__ __align__(256) double scratch[DIAG_SCRATCH_BLOCKS * 8];
 
 namespace {
 
@@ -306,6 +310,29 @@ int macro_into(lbm_sim *s, void *rho, void *u, int fp64, unsigned int *bad) {
     }
     const MacroParams m = macro_params(s, rho, u, fp64, bad);
     HIPCHK(s, launch_macro(s->lattice, s->storage, m, node_cfg(s)));
+    return LBM_OK;
+}
+
+// Scratch of lbm_diag_noalloc: the partial sums of its fused reduction (DIAG_SCRATCH_BLOCKS
+// sets of 8 doubles) in a static device array, one copy per GPU, held until the process
+// ends (131 KB).  Its size does not depend on the lattice: the reduction walks the nodes
+// with a fixed grid.  Host code never uses the array's name as an address (it is a
+// host-side stand-in): the device address is taken with hipGetSymbolAddress once per
+// device, with that device current, and kept.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+int diag_scratch(lbm_sim *s, double **out) {
+    if (s->device < 0 || s->device >= MAX_DEVICES) return fail(s, LBM_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[s->device]) {
+        HIPCHK(s, hipSetDevice(s->device));
+        void *ptr = nullptr;
+        HIPCHK(s, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[s->device] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[s->device];
     return LBM_OK;
 }
 
@@ -676,6 +703,23 @@ int lbm_elbm_stats(lbm_sim *s, int enable, int reset, int64_t *hist, int nbins, 
     }
     if (reset) HIPCHK(s, hipMemsetAsync(s->stats_d, 0, sizeof(unsigned long long) * (NEWTON_BINS + 1), s->stream));
     s->stats_on = enable != 0;
+    return LBM_OK;
+}
+
+int lbm_diag_noalloc(lbm_sim *s, void *out_dev) {
+    if (!s) return fail(nullptr, LBM_EINVAL, "sim is NULL");
+    if (!out_dev) return fail(s, LBM_EINVAL, "out_dev is NULL");
+    if (!s->ready) return fail(s, LBM_ESTATE, "no state yet: call lbm_init_eq or lbm_set_f");
+    double *partials = nullptr;
+    int rc = diag_scratch(s, &partials);
+    if (rc) return rc;
+    if (s->model == LBM_SHANCHEN) {
+        rc = run_psi(s);
+        if (rc) return rc;
+    }
+    MacroParams m = macro_params(s, nullptr, nullptr, 1, nullptr);
+    HIPCHK(s, launch_diag_fused(s->lattice, s->storage, m, partials, DIAG_SCRATCH_BLOCKS, static_cast<double *>(out_dev),
+                                s->stream));
     return LBM_OK;
 }
 

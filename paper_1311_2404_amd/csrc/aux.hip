@@ -150,15 +150,16 @@ __global__ void k_set_plane(PlaneParams p) {
 // shifted FP32), which made the output and the diagnostics built on it 4-5x slower.
 enum { MK_ONE = 0, MK_SC = 1, MK_FE = 2 };
 
+// The macroscopic values of node n: rho[0..NC) and v[3]; returns false where a density is
+// non-finite or non-positive (phi of the free-energy model only has to be finite).
 template <class L, class St, int KIND, bool FL>
-__global__ __launch_bounds__(256) void k_macro(MacroParams p) {
+__device__ __forceinline__ bool macro_node(const MacroParams &p, uint32_t n, double *rho, double *v) {
     using T = typename St::T;
     using C = typename St::C;
     constexpr int NC = KIND == MK_ONE ? 1 : 2;
-    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= p.N) return;
     const Geo g = geo_of(n, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
-    double rho[2] = {0.0, 0.0}, j[3] = {0.0, 0.0, 0.0}, jf[3] = {0.0, 0.0, 0.0};
+    double j[3] = {0.0, 0.0, 0.0}, jf[3] = {0.0, 0.0, 0.0};
+    rho[0] = rho[1] = 0.0;
     const uint32_t fl = FL ? p.flags[n] : 0u;
     const bool vel = FL && KIND == MK_ONE && fl == 2u;
     const bool half = FL && KIND != MK_SC && fl == 3u;
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void k_macro(MacroParams p) {
         j[1] += double(m.jy);
         j[2] += double(m.jz);
     }
-    double v[3] = {0.0, 0.0, 0.0};
+    v[0] = v[1] = v[2] = 0.0;
     const bool wall = fl == 1u;
     if (KIND == MK_FE) {
         // rho[1] is phi (the g lattice's zeroth moment); velocity (j + F/2)/rho of f alone
@@ -261,12 +262,20 @@ __global__ __launch_bounds__(256) void k_macro(MacroParams p) {
             for (int k = 0; k < 3; k++) v[k] = (j[k] + hf * rho[0] * p.g[k]) / rho[0];
         }
     }
-    if (p.bad) {
-        bool ok = (rho[0] > 0.0) && isfinite(rho[0]);
-        if (KIND == MK_SC) ok = ok && (rho[1] > 0.0) && isfinite(rho[1]);
-        if (KIND == MK_FE) ok = ok && isfinite(rho[1]);
-        if (!ok) atomicAdd(p.bad, 1u);
-    }
+    bool ok = (rho[0] > 0.0) && isfinite(rho[0]);
+    if (KIND == MK_SC) ok = ok && (rho[1] > 0.0) && isfinite(rho[1]);
+    if (KIND == MK_FE) ok = ok && isfinite(rho[1]);
+    return ok;
+}
+
+template <class L, class St, int KIND, bool FL>
+__global__ __launch_bounds__(256) void k_macro(MacroParams p) {
+    constexpr int NC = KIND == MK_ONE ? 1 : 2;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.N) return;
+    double rho[2], v[3];
+    const bool ok = macro_node<L, St, KIND, FL>(p, n, rho, v);
+    if (p.bad && !ok) atomicAdd(p.bad, 1u);
     if (p.fp64) {
         double *ro = static_cast<double *>(p.rho_out), *uo = static_cast<double *>(p.u_out);
 #pragma unroll
@@ -301,6 +310,38 @@ __global__ __launch_bounds__(RED_BS) void k_diag_partials(const double *rho, con
         acc[4] += rt * uz;
         acc[5] += ux * ux + uy * uy + uz * uz;
         bool ok = (r0 > 0.0) && isfinite(r0) && (ncomp == 1 || ((phi2 || r1 > 0.0) && isfinite(r1)));
+        acc[6] += ok ? 0.0 : 1.0;
+    }
+    for (int k = 0; k < RED_K; k++) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = RED_BS / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < RED_K; k++) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < RED_K) partials[size_t(blockIdx.x) * RED_K + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// The diagnostics without the FP64 field pass: each thread takes the macroscopic values of
+// its nodes (grid-stride, nodes n = b RED_BS + t + k gridDim.x RED_BS) straight from the
+// populations and adds them to its sums in the same fixed order as k_diag_partials; the
+// block's tree in LDS writes one set of partial sums.  Nothing is accumulated across
+// calls, so the partials need no clearing.
+template <class L, class St, int KIND, bool FL>
+__global__ __launch_bounds__(RED_BS) void k_diag_fused(MacroParams p, double *partials) {
+    __shared__ double s[RED_K][RED_BS];
+    double acc[RED_K] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (uint32_t n = blockIdx.x * RED_BS + threadIdx.x; n < p.N; n += gridDim.x * RED_BS) {
+        double rho[2], v[3];
+        const bool ok = macro_node<L, St, KIND, FL>(p, n, rho, v);
+        const double r1 = KIND == MK_ONE ? 0.0 : rho[1];
+        const double rt = KIND == MK_SC ? rho[0] + r1 : rho[0];
+        acc[0] += rho[0];
+        acc[1] += r1;
+        acc[2] += rt * v[0];
+        acc[3] += rt * v[1];
+        acc[4] += rt * v[2];
+        acc[5] += v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         acc[6] += ok ? 0.0 : 1.0;
     }
     for (int k = 0; k < RED_K; k++) s[k][threadIdx.x] = acc[k];
@@ -379,6 +420,31 @@ hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, in
                               int nblocks, double *out, hipStream_t s) {
     k_diag_partials<<<nblocks, RED_BS, 0, s>>>(rho, u, N, ncomp, phi2, partials);
     k_diag_final<<<1, RED_BS, 0, s>>>(partials, nblocks, N, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_fused(int lattice, int storage, const MacroParams &p, double *partials, int nblocks,
+                             double *out, hipStream_t st) {
+    hipError_t e = with_lattice(lattice, [&](auto lt) {
+        using L = decltype(lt);
+        return with_storage<false>(storage, 0, [&](auto sto) {
+            using St = decltype(sto);
+            const bool fl = p.flags != nullptr;
+            if (p.model == M_SC) {
+                if (fl) k_diag_fused<L, St, MK_SC, true><<<nblocks, RED_BS, 0, st>>>(p, partials);
+                else k_diag_fused<L, St, MK_SC, false><<<nblocks, RED_BS, 0, st>>>(p, partials);
+            } else if (p.model == M_FE) {
+                if (fl) k_diag_fused<L, St, MK_FE, true><<<nblocks, RED_BS, 0, st>>>(p, partials);
+                else k_diag_fused<L, St, MK_FE, false><<<nblocks, RED_BS, 0, st>>>(p, partials);
+            } else {
+                if (fl) k_diag_fused<L, St, MK_ONE, true><<<nblocks, RED_BS, 0, st>>>(p, partials);
+                else k_diag_fused<L, St, MK_ONE, false><<<nblocks, RED_BS, 0, st>>>(p, partials);
+            }
+            return hipGetLastError();
+        });
+    });
+    if (e != hipSuccess) return e;
+    k_diag_final<<<1, RED_BS, 0, st>>>(partials, nblocks, p.N, out);
     return hipGetLastError();
 }
 

@@ -132,6 +132,10 @@ hipError_t launch_macro(int lattice, int storage, const MacroParams &p, const La
 // deterministic FP64 reduction of (rho[C][N], u[3][N]) into out[8]
 hipError_t launch_diag_reduce(const double *rho, const double *u, uint32_t N, int ncomp, int phi2, double *partials,
                               int nblocks, double *out, hipStream_t s);
+// the same sums taken straight from the populations (no field pass): nblocks partial sets
+// of 8 doubles in partials[], the result in out[8]
+hipError_t launch_diag_fused(int lattice, int storage, const MacroParams &p, double *partials, int nblocks,
+                             double *out, hipStream_t s);
 
 // MLP kernels (mlp.hip)
 struct MlpDatasetParams {
