@@ -94,78 +94,38 @@ def _time_steps(sim, stream, torch, steps):
     return e0.elapsed_time(e1) / steps
 
 
-def entropic_profile(P, S, stream, torch, steps, warmup):
+def entropic_profile(P, S, stream, torch, steps, warmup, alpha_init=1):
     """The entropic step alone, for kernel traces and counter passes: the 256^3 vortex in
-    FP32 storage, AB, Newton from the series first guess.  `warmup` steps run with the
-    Newton statistics on; then `steps` steps are timed without them."""
+    FP32 storage, AB, Newton from the series first guess (alpha_init 1), from 2 (0) or from
+    the network's (2; the untrained network of mlp_initial_weights, whose zero output layer
+    proposes the series estimate, so the instruction mix is the network's and the
+    iterations are the series').  `warmup` steps run with the Newton statistics on; then
+    `steps` steps are timed without them."""
     c4 = S.c4_elbm_taylor_green(n=256)
     s = P.Sim.from_case(c4, P.LBM_F32, P.LBM_AB, stream=stream)
-    P.lbm_set_elbm(s.h, 1, 1e-10, 20)
+    if alpha_init == 2:
+        P.lbm_mlp_set_weights(s.h, P.mlp_initial_weights(20131124))
+    P.lbm_set_elbm(s.h, alpha_init, 1e-10, 20)
     P.lbm_elbm_stats(s.h, enable=True, reset=True)
     s.step(warmup)
     hist, nonconv = P.lbm_elbm_stats(s.h, enable=False)
     ms = _time_steps(s, stream, torch, steps)
     s.close()
     k = np.arange(len(hist))
+    guess = ("2", "the series guess", "the network's guess")[alpha_init]
     return {"workload": "D3Q19 entropic LBM 256^3 vortex, u0=0.05, nu=1e-5, FP32 storage, AB, "
-                        "Newton from the series guess", "nodes": c4.n, "warmup": warmup, "steps": steps,
+                        "Newton from " + guess, "nodes": c4.n, "warmup": warmup, "steps": steps,
+            "alpha_init": alpha_init,
             "mlups": round(c4.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
             "warmup_mean_newton_iters": round(float((k * hist).sum() / max(hist.sum(), 1)), 4),
             "warmup_nonconverged": int(nonconv)}
 
 
-def run_extras(P, S, stream, torch):
-    """The other measured configurations (throughput and stated errors), one GPU."""
-    out = {}
-    # D3Q19 MRT duct 128x128x512, 5000 steps: each storage's velocity error vs FP64
-    c3 = S.c3_duct(128, 128, 512, steps=5000)
-    us, rows = {}, {}
-    for st, sr in [(P.LBM_F64, 0), (P.LBM_F32, 0), (P.LBM_F32S, 0), (P.LBM_BF16S, 0), (P.LBM_BF16S, 1),
-                   (P.LBM_F16S, 0), (P.LBM_F16S, 1)]:
-        s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
-        ms = _time_steps(s, stream, torch, 200)
-        s.close()
-        s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
-        s.step(c3.steps)
-        us[(st, sr)] = s.macro()[1]
-        s.close()
-        b = bytes_per_node(st) + 1  # populations read and written, plus the flag byte
-        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")] = {
-            "mlups": round(c3.n / ms / 1e3, 1), "bytes_per_node": b,
-            "hbm_gbs_algorithmic": round(b * c3.n / (ms * 1e-3) / 1e9, 1)}
-    ref = us[(P.LBM_F64, 0)]
-    for (st, sr), u in us.items():
-        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")]["vel_rel_l2_vs_fp64"] = float(
-            np.linalg.norm(u - ref) / np.linalg.norm(ref))
-    out["d3q19_mrt_duct_128x128x512_5000_steps"] = rows
-    print("[bench] MRT duct done", file=sys.stderr, flush=True)
-
-    # Diagnostics (kinetic energy, mass, momentum) on the 256^3 Taylor-Green state: one call
-    # is the macroscopic pass (populations in, FP64 rho and u out), the two-stage FP64
-    # reduction over those fields and the copy of the 8 sums to the host
-    c2 = S.c2_taylor_green(n=256)
-    diag = {}
-    for st in (P.LBM_F32, P.LBM_F32S, P.LBM_BF16S):
-        s = P.Sim.from_case(c2, st, P.LBM_AB, stream=stream)
-        s.diag()
-        t0 = time.perf_counter()
-        for _ in range(20):
-            s.diag()
-        ms = (time.perf_counter() - t0) / 20 * 1e3
-        s.close()
-        b = bytes_per_node(st) // 2 + 4 * 8 + 4 * 8  # populations read, FP64 rho and u written, read back
-        diag[P.STORAGE_NAMES[st]] = {"ms_per_call": round(ms, 4), "bytes_per_node": b,
-                                     "hbm_gbs_algorithmic": round(b * c2.n / (ms * 1e-3) / 1e9, 1)}
-    out["d3q19_diagnostics_256"] = diag
-    del c2
-    print("[bench] diagnostics done", file=sys.stderr, flush=True)
-
-    # D3Q19 entropic LBM 256^3 (u0 0.05, nu 1e-5), run to 8000 steps with Newton from the
-    # series estimate.  (state, alpha) pairs are drawn every 500 steps (alpha from Newton
-    # from 2), the network trains on 90% of them, and each first guess (2, series, MLP) is
-    # timed over 100 steps from the state at step 1000 (alpha close to 2) and at step
-    # 8000 (alpha departs from 2; max |d_i| passes 0.1 at 9% of the nodes, where the
-    # condition takes its logarithmic form), with its Newton histogram
+def elbm_regimes(P, S, stream, torch):
+    """D3Q19 entropic LBM 256^3 (u0 0.05, nu 1e-5), run to 8000 steps with Newton from the
+    series estimate: (state, alpha) pairs every 500 steps, the network trained on 90% of
+    them, and each first guess (2, series, MLP) timed over 100 steps from the states at
+    steps 1000 and 8000, with its Newton histogram."""
     c4 = S.c4_elbm_taylor_green(n=256)
     s = P.Sim.from_case(c4, P.LBM_F32, P.LBM_AB, stream=stream)
     P.lbm_set_elbm(s.h, 1, 1e-10, 20)
@@ -238,7 +198,56 @@ def run_extras(P, S, stream, torch):
                                           "simd_cycles_per_node": rec["simd_cycles_per_node"]}
         elbm["from_step_%d" % step_no] = rows
     s.close()
-    out["d3q19_elbm_taylor_green_256_fp32"] = elbm
+    return elbm
+
+
+def run_extras(P, S, stream, torch):
+    """The other measured configurations (throughput and stated errors), one GPU."""
+    out = {}
+    # D3Q19 MRT duct 128x128x512, 5000 steps: each storage's velocity error vs FP64
+    c3 = S.c3_duct(128, 128, 512, steps=5000)
+    us, rows = {}, {}
+    for st, sr in [(P.LBM_F64, 0), (P.LBM_F32, 0), (P.LBM_F32S, 0), (P.LBM_BF16S, 0), (P.LBM_BF16S, 1),
+                   (P.LBM_F16S, 0), (P.LBM_F16S, 1)]:
+        s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
+        ms = _time_steps(s, stream, torch, 200)
+        s.close()
+        s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
+        s.step(c3.steps)
+        us[(st, sr)] = s.macro()[1]
+        s.close()
+        b = bytes_per_node(st) + 1  # populations read and written, plus the flag byte
+        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")] = {
+            "mlups": round(c3.n / ms / 1e3, 1), "bytes_per_node": b,
+            "hbm_gbs_algorithmic": round(b * c3.n / (ms * 1e-3) / 1e9, 1)}
+    ref = us[(P.LBM_F64, 0)]
+    for (st, sr), u in us.items():
+        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")]["vel_rel_l2_vs_fp64"] = float(
+            np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    out["d3q19_mrt_duct_128x128x512_5000_steps"] = rows
+    print("[bench] MRT duct done", file=sys.stderr, flush=True)
+
+    # Diagnostics (kinetic energy, mass, momentum) on the 256^3 Taylor-Green state: one call
+    # is the macroscopic pass (populations in, FP64 rho and u out), the two-stage FP64
+    # reduction over those fields and the copy of the 8 sums to the host
+    c2 = S.c2_taylor_green(n=256)
+    diag = {}
+    for st in (P.LBM_F32, P.LBM_F32S, P.LBM_BF16S):
+        s = P.Sim.from_case(c2, st, P.LBM_AB, stream=stream)
+        s.diag()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            s.diag()
+        ms = (time.perf_counter() - t0) / 20 * 1e3
+        s.close()
+        b = bytes_per_node(st) // 2 + 4 * 8 + 4 * 8  # populations read, FP64 rho and u written, read back
+        diag[P.STORAGE_NAMES[st]] = {"ms_per_call": round(ms, 4), "bytes_per_node": b,
+                                     "hbm_gbs_algorithmic": round(b * c2.n / (ms * 1e-3) / 1e9, 1)}
+    out["d3q19_diagnostics_256"] = diag
+    del c2
+    print("[bench] diagnostics done", file=sys.stderr, flush=True)
+
+    out["d3q19_elbm_taylor_green_256_fp32"] = elbm_regimes(P, S, stream, torch)
     print("[bench] ELBM done", file=sys.stderr, flush=True)
 
     # D3Q19 two-component Shan-Chen 384^3, FP32 compute: throughput and per-component
@@ -394,6 +403,11 @@ def main():
                     help="run only the D2Q9 Taylor-Green precision study over u0 and storages (JSON line)")
     ap.add_argument("--entropic-profile", action="store_true",
                     help="run only the entropic 256^3 step (series guess), for traces and counters (JSON line)")
+    ap.add_argument("--alpha-init", type=int, default=1, choices=[0, 1, 2],
+                    help="first guess of the alpha solve for --entropic-profile (0: 2, 1: series, 2: network)")
+    ap.add_argument("--elbm-regimes", action="store_true",
+                    help="run only the entropic 256^3 vortex to 8000 steps: MLP training and the first guesses "
+                         "timed at steps 1000 and 8000 (JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -416,7 +430,10 @@ def main():
                           "wall_s": round(time.perf_counter() - t0, 1)}))
         return
     if args.entropic_profile:
-        print(json.dumps(entropic_profile(P, S, stream, torch, args.steps, args.warmup)))
+        print(json.dumps(entropic_profile(P, S, stream, torch, args.steps, args.warmup, args.alpha_init)))
+        return
+    if args.elbm_regimes:
+        print(json.dumps(elbm_regimes(P, S, stream, torch)))
         return
     layout = P.LBM_AA if args.layout == "aa" else P.LBM_AB
     n = args.n

@@ -1,6 +1,7 @@
 // Auxiliary kernels: equilibrium initialisation, population plane transfer in the
 // canonical (physical) layout, macroscopic output and deterministic FP64 diagnostics.
 #include "dispatch.hpp"
+#include "elbm.hpp"
 #include "step.hpp"
 
 namespace lbm {

@@ -45,6 +45,128 @@
 
 namespace lbm {
 
+// Discrete entropic equilibrium p_i = w_i exp(b.e_i)/Z: the minimiser of
+// H = sum f ln(f/w) at fixed rho and rho u.  exp(b.e_i) is a product of per-axis
+// factors, so the state is kept as E+_a = expm1(b_a), E-_a = expm1(-b_a).  Start:
+// the product-form base (2u + sqrt(1+3u^2))/(1-u) per axis (entropic LBM subsection,
+// with the factor 3 under the root); then Newton steps on the momentum constraint,
+// Jacobian = covariance of e under p: two in FP64, one in FP32, where the seed's error
+// (~1e-6 relative at |u| = 0.05) is squared by the first step to below 2e-11 of w_i
+// for |u| <= 0.15, three orders under FP32 resolution, so a second step changes nothing
+// FP32 can hold.  Output heq_i = rho p_i - w_i (shifted space), formed from expm1
+// values so the small deviation keeps its relative accuracy.
+//
+// In FP32 the quotients take the hardware reciprocal (1 ulp) instead of the correctly
+// rounded division sequence, and the Newton correction's expm1(+-d) its cubic Taylor
+// polynomial: |d| stays below 1e-4 for |u| <= 0.15 (the seed misses the momentum by
+// ~1e-5 relative), where the dropped d^4/24 is ~1e-18 of d.  The FP64 path keeps the
+// divisions and expm1 of the definition.
+template <class C>
+__device__ __forceinline__ C eq_div(C a, C b) {
+    if constexpr (sizeof(C) == 4) return a * __builtin_amdgcn_rcpf(b);
+    else return a / b;
+}
+template <class C>
+__device__ __forceinline__ C eq_expm1_small(C d) {
+    if constexpr (sizeof(C) == 4) return d * fmaf(d, fmaf(d, 1.0f / 6.0f, 0.5f), 1.0f);
+    else return expm1(d);
+}
+
+template <class L, class C>
+__device__ __forceinline__ void entropic_heq(C drho, C rho, C ux, C uy, C uz, C *heq) {
+    C Ep[3], Em[3];
+    const C u[3] = {ux, uy, uz};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a >= L::D) {
+            Ep[a] = Em[a] = C(0);
+            continue;
+        }
+        const C s = sqrt(C(1) + C(3) * u[a] * u[a]);
+        const C t = C(3) * u[a] + C(3) * u[a] * u[a] / (s + C(1));  // 2u + s - (1 - u)
+        Ep[a] = eq_div<C>(t, C(1) - u[a]);
+        Em[a] = eq_div<C>(-t, C(2) * u[a] + s);
+    }
+    auto em1 = [&](int i) -> C {  // expm1(b . e_i)
+        C r = C(0);
+        int na = 0;
+        C fac[3];
+        const int e[3] = {L::ex(i), L::ey(i), L::ez(i)};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (e[a] == 1) fac[na++] = Ep[a];
+            if (e[a] == -1) fac[na++] = Em[a];
+        }
+        if (na == 1) r = fac[0];
+        if (na == 2) r = fac[0] + fac[1] + fac[0] * fac[1];
+        return r;
+    };
+    constexpr int NEWTON = sizeof(C) == 8 ? 2 : 1;
+    C dp[L::Q];  // p_i - w_i
+    for (int it = 0; it <= NEWTON; it++) {
+        C zm1 = C(0);
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) zm1 += C(L::w(i)) * em1(i);
+        const C iz = eq_div<C>(C(1), C(1) + zm1);
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) dp[i] = C(L::w(i)) * (em1(i) - zm1) * iz;
+        if (it == NEWTON) break;
+        // mean and covariance of e under p
+        C m[3] = {C(0), C(0), C(0)}, Cv[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) Cv[a][b] = (a == b && a < L::D) ? C(1.0 / 3.0) : C(0);
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) {
+            const int e[3] = {L::ex(i), L::ey(i), L::ez(i)};
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                if (e[a]) m[a] += C(e[a]) * dp[i];
+#pragma unroll
+                for (int b = 0; b < 3; b++)
+                    if (e[a] * e[b]) Cv[a][b] += C(e[a] * e[b]) * dp[i];
+            }
+        }
+        C r[3], d[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            r[a] = m[a] - u[a];
+#pragma unroll
+            for (int b = 0; b < 3; b++) Cv[a][b] -= m[a] * m[b];
+        }
+        if constexpr (L::D == 2) {
+            const C det = Cv[0][0] * Cv[1][1] - Cv[0][1] * Cv[1][0];
+            const C idet = eq_div<C>(C(1), det);
+            d[0] = (r[0] * Cv[1][1] - Cv[0][1] * r[1]) * idet;
+            d[1] = (Cv[0][0] * r[1] - r[0] * Cv[1][0]) * idet;
+            d[2] = C(0);
+        } else {
+            // inverse of the symmetric 3x3 covariance by cofactors
+            const C c00 = Cv[1][1] * Cv[2][2] - Cv[1][2] * Cv[2][1];
+            const C c01 = Cv[1][2] * Cv[2][0] - Cv[1][0] * Cv[2][2];
+            const C c02 = Cv[1][0] * Cv[2][1] - Cv[1][1] * Cv[2][0];
+            const C c11 = Cv[0][0] * Cv[2][2] - Cv[0][2] * Cv[2][0];
+            const C c12 = Cv[0][1] * Cv[2][0] - Cv[0][0] * Cv[2][1];
+            const C c22 = Cv[0][0] * Cv[1][1] - Cv[0][1] * Cv[1][0];
+            const C idet = eq_div<C>(C(1), Cv[0][0] * c00 + Cv[0][1] * c01 + Cv[0][2] * c02);
+            d[0] = (c00 * r[0] + c01 * r[1] + c02 * r[2]) * idet;
+            d[1] = (c01 * r[0] + c11 * r[1] + c12 * r[2]) * idet;
+            d[2] = (c02 * r[0] + c12 * r[1] + c22 * r[2]) * idet;
+        }
+        // b_a -= d_a  =>  E+ = E+ + (1+E+) expm1(-d), E- = E- + (1+E-) expm1(d)
+#pragma unroll
+        for (int a = 0; a < L::D; a++) {
+            const C em = eq_expm1_small<C>(-d[a]), ep = eq_expm1_small<C>(d[a]);
+            Ep[a] = Ep[a] + (C(1) + Ep[a]) * em;
+            Em[a] = Em[a] + (C(1) + Em[a]) * ep;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) heq[i] = rho * dp[i] + drho * C(L::w(i));
+}
+
+
 struct AlphaOut {
     double alpha;
     int iters;
@@ -108,6 +230,31 @@ __device__ __forceinline__ bool alpha_needs_khi(const C *h, const C *heq) {
 #pragma unroll
     for (int i = 0; i < L::Q; i++) big |= fabs(heq[i] - h[i]) > fma(m6, h[i], C(m6 * L::w(i)));
     return __builtin_amdgcn_ballot_w64(big) != 0;
+}
+
+// log1p(x) in FP64 for x > -1, within a few ulp (host check against the C library over
+// x in (-1, 20): at most 5 ulp, 0.4-0.8 ulp on average): u = 1 + x = m 2^k with m in
+// [sqrt(1/2), sqrt(2)), log u = k ln 2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| < 0.1716,
+// from the odd Taylor series 2 s (1 + s^2/3 + ... + s^20/21) (the next term is below
+// 2^-60 of the sum); then log1p(x) = log(u) x / (u - 1), which undoes the rounding of
+// u = 1 + x to first order (the classical correction for small x).  About 40
+// instructions, against 135 for the library's double-double log1p.
+__device__ __forceinline__ double log1p_series(double x) {
+    const double u = 1.0 + x;
+    if (u == 1.0) return x;
+    int k;
+    double m = frexp(u, &k);
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        k -= 1;
+    }
+    const double s = (m - 1.0) * recip(m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 21.0;
+#pragma unroll
+    for (int j = 9; j >= 0; j--) p = fma(p, s2, 1.0 / double(2 * j + 1));
+    const double lg = fma(double(k), 0.69314718055994530942, 2.0 * s * p);
+    return lg * (x * recip(u - 1.0));
 }
 
 // the raw mass and momentum of heq - h (removed from D by alpha_D)
@@ -222,9 +369,9 @@ __device__ __forceinline__ AlphaOut alpha_newton_log(const C *h, const C *heq, c
 #pragma unroll 1
         for (int i = 0; i < L::Q; i++) {
             const double f = fl[i], d = dl[i];
-            const double l1 = log1p(d);
+            const double l1 = log1p_series(d);
             const double ad = a * d;
-            const double la = log1p(ad);
+            const double la = log1p_series(ad);
             const double t1 = f * (1.0 + ad) * la, t2 = f * ad * l1;
             g += t1 - t2;
             dg += f * d * (la - l1);

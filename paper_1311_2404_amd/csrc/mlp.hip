@@ -9,6 +9,7 @@
 // wave with lane shuffles, then across the waves of a block and across blocks in a
 // fixed order, so a training run is deterministic.
 #include "dispatch.hpp"
+#include "elbm.hpp"
 #include "step.hpp"
 
 namespace lbm {

@@ -1,5 +1,7 @@
-// The fused stream-and-collide kernel (one thread per node) and its two-component
-// Shan-Chen variant.
+// The fused stream-and-collide kernel of the polynomial-equilibrium models (one thread
+// per node) and what every step kernel shares: the streaming patterns, the population
+// addresses, the boundary-node rules and the divergence flag.  The entropic step is in
+// step_elbm.hpp, the two-component Shan-Chen kernels in step_sc.hpp.
 //
 // Streaming patterns (GPU-algorithms subsection of the paper, AB and AA):
 //   AB      : read the population arriving along e_i from node x - e_i of copy A
@@ -21,7 +23,6 @@
 #include <type_traits>
 
 #include "collide.hpp"
-#include "elbm.hpp"
 #include "lattice.hpp"
 #include "params.hpp"
 #include "storage.hpp"
@@ -309,300 +310,6 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         }
         raise_divergence(p, bad);
     }
-}
-
-// Nodes whose alpha needs the logarithmic form (max |d_i| > ALPHA_SERIES_DMAX) are few
-// but spread: at step 8000 of the 256^3 entropic vortex 9% of the nodes, so nearly every
-// wave has some, and a divergent branch would run every wave through the logarithms for
-// a few lanes.  Such nodes are queued in LDS instead (f_i, d_i, the first guess and a_max
-// of each) and the workgroup's first wave solves them with its lanes packed, log1p(d_i)
-// included; each queued node then reads its alpha back.  A queue entry takes 472 bytes;
-// nodes beyond the capacity solve in place.
-constexpr int ALPHA_LOGQ = 64;
-
-template <int Q>
-struct AlphaLogQueue {
-    double f[Q][ALPHA_LOGQ], d[Q][ALPHA_LOGQ], l1[Q][ALPHA_LOGQ];
-    double a0[ALPHA_LOGQ], amax[ALPHA_LOGQ], alpha[ALPHA_LOGQ];
-    int iters[ALPHA_LOGQ], conv[ALPHA_LOGQ];
-    int count;
-};
-
-// Newton with bisection safeguard on the logarithmic form of g for queue entry e: the
-// iteration of alpha_newton_log, with log1p(d_i) taken once per node instead of once per
-// iteration.
-template <int Q>
-__device__ __forceinline__ void alpha_newton_log_queued(AlphaLogQueue<Q> &sq, int e, double tol, int maxit) {
-#pragma unroll 1
-    for (int i = 0; i < Q; i++) sq.l1[i][e] = log1p(sq.d[i][e]);
-    double lo = 1.0, hi = sq.amax[e], a = sq.a0[e];
-    if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
-    for (int k = 1; k <= maxit; k++) {
-        double g = 0.0, dg = 0.0, gs = 0.0;
-#pragma unroll 1
-        for (int i = 0; i < Q; i++) {
-            const double f = sq.f[i][e], d = sq.d[i][e], l1 = sq.l1[i][e];
-            const double ad = a * d;
-            const double la = log1p(ad);
-            const double t1 = f * (1.0 + ad) * la, t2 = f * ad * l1;
-            g += t1 - t2;
-            dg += f * d * (la - l1);
-            gs += fabs(t1) + fabs(t2);
-        }
-        if (fabs(g) <= 64.0 * 2.220446049250313e-16 * gs) {
-            sq.alpha[e] = a, sq.iters[e] = k, sq.conv[e] = 1;
-            return;
-        }
-        if (g < 0.0) lo = a; else hi = a;
-        double an = a - g / dg;
-        if (fabs(an - a) <= tol) {
-            sq.alpha[e] = an, sq.iters[e] = k, sq.conv[e] = 1;
-            return;
-        }
-        if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
-        a = an;
-    }
-    sq.alpha[e] = fmin(2.0, 0.99 * sq.amax[e]), sq.iters[e] = maxit, sq.conv[e] = 0;
-}
-
-// The entropic step.  One x row (segment) per workgroup; every lane of the workgroup runs
-// the whole kernel (lanes past the row's end on a clamped node, storing nothing; wall
-// nodes and nodes at the alpha = 2 short-cut keep their own result), because the MLP
-// first guess runs on the matrix cores for the 64 nodes of a wave at once and the
-// logarithmic fallback is shared through LDS.  MLP: alpha_init = 2 (the network's guess,
-// skipped in waves where no lane needs a solve); otherwise alpha_init 0 (alpha0 = 2) or
-// 1 (the series estimate).
-template <class L, class St, int LAYOUT, bool FLAGS, bool MLP>
-__global__ __launch_bounds__(512) void k_step_elbm(StepParams p) {
-    using T = typename St::T;
-    using C = typename St::C;
-    constexpr int Q = L::Q;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
-    const int z = blockIdx.z;
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    __shared__ uint32_t s_hist[NEWTON_BINS + 1];
-    __shared__ AlphaLogQueue<Q> sq;
-    if (tid == 0) sq.count = 0;
-    if (p.stats)
-        for (int k = tid; k < NEWTON_BINS + 1; k += nthr) s_hist[k] = 0u;
-    __syncthreads();
-    const bool active = x < p.nx;
-    const Geo g = make_geo(active ? x : p.nx - 1, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
-    const uint32_t n = g.at(0, 0, 0);
-    const uint32_t S = p.S;
-    const T *src = static_cast<const T *>(p.src);
-    T *dst = static_cast<T *>(p.dst);
-    T raw[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        int slot, dx, dy, dz;
-        canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        raw[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
-    }
-    const bool wall = FLAGS && p.flags[n] == 1;
-    C h[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) h[i] = St::decode(raw[i], C(L::w(i)));
-    const Macro<C> m = moments<L, C>(h);
-    const C irho = C(1) / m.rho;
-    const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
-    C heq[Q];
-    entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
-    AlphaNode an;
-    alpha_project<L, C>(h, heq, an);
-    double a0 = 2.0;
-    if constexpr (MLP) {
-        // the features first, so that the moments are not live across the network
-        const double vsq = double(vx) * double(vx) + double(vy) * double(vy) + double(vz) * double(vz);
-        float xf[MLP_IN];
-        const double dmax = alpha_feature_pass<L, C>(h, heq, an, double(m.rho), vsq, xf);
-        const bool want = active && !wall && dmax >= ALPHA_SHORTCUT;
-#pragma unroll
-        for (int k = 0; k < MLP_IN; k++) xf[k] = want ? xf[k] : 0.0f;
-        // all lanes of the wave, and only in waves where some lane needs the solve (the
-        // condition is wave-uniform: a scalar branch, EXEC unchanged)
-        if (__builtin_amdgcn_ballot_w64(want) != 0) a0 = double(mlp_eval_wave(p.mlp_lane, p.mlp_wf, xf));
-    }
-    alpha_moments<L, C>(h, heq, an);
-    const bool solve = active && !wall && an.dmax >= ALPHA_SHORTCUT;
-    if constexpr (!MLP) {
-        if (p.alpha_init == 1) a0 = 2.0 + (an.am[3] - 2.0 * an.am[4]) / (3.0 * an.am[2]);
-    }
-    AlphaOut ao{2.0, 0, 1};
-    const bool logf = solve && an.dmax > ALPHA_SERIES_DMAX;
-    if (solve && !logf) {
-        if (an.khi) ao = alpha_newton_moments<ALPHA_K>(an.am, a0, 2.5, p.alpha_tol, p.alpha_maxit);
-        else ao = alpha_newton_moments<ALPHA_K_LO>(an.am, a0, 2.5, p.alpha_tol, p.alpha_maxit);
-    }
-    int qslot = -1;
-    if (logf) {
-        qslot = atomicAdd(&sq.count, 1);
-        if (qslot < ALPHA_LOGQ) {
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                const double f = L::w(i) + double(h[i]);
-                sq.f[i][qslot] = f;
-                sq.d[i][qslot] = alpha_D<L, C>(h, heq, an, i) * recip<C>(f);
-            }
-            sq.a0[qslot] = a0;
-            sq.amax[qslot] = an.amax;
-        } else {
-            ao = alpha_newton_log<L, C>(h, heq, an, a0, p.alpha_tol, p.alpha_maxit);
-        }
-    }
-    __syncthreads();
-    const int nq = min(sq.count, ALPHA_LOGQ);
-    for (int e = tid; e < nq; e += nthr) alpha_newton_log_queued<Q>(sq, e, p.alpha_tol, p.alpha_maxit);
-    __syncthreads();
-    if (qslot >= 0 && qslot < ALPHA_LOGQ) ao = AlphaOut{sq.alpha[qslot], sq.iters[qslot], sq.conv[qslot]};
-    T out[Q];
-    bool bad = false;
-    if (wall) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) out[i] = raw[opp(i)];
-    } else {
-        const C ab = C(ao.alpha * p.beta);
-        C o[Q];
-#pragma unroll
-        for (int i = 0; i < Q; i++) o[i] = h[i] + ab * (heq[i] - h[i]);
-        conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
-        bad = nonfinite<C>(o[0]);
-#pragma unroll
-        for (int i = 0; i < Q; i++) out[i] = St::encode(o[i], C(L::w(i)), 0u);
-        if (p.stats && active) {
-            atomicAdd(&s_hist[ao.iters < NEWTON_BINS ? ao.iters : NEWTON_BINS - 1], 1u);
-            if (!ao.converged) atomicAdd(&s_hist[NEWTON_BINS], 1u);
-        }
-    }
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            int slot, dx, dy, dz;
-            post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), out[i], i);
-        }
-        raise_divergence(p, bad);
-    }
-    if (p.stats) {
-        __syncthreads();
-        for (int k = tid; k < NEWTON_BINS + 1; k += nthr)
-            if (s_hist[k]) atomicAdd(&p.stats[k], (unsigned long long)s_hist[k]);
-    }
-}
-
-// Shan-Chen pre-pass (the paper's macroscopic-field kernel): psi_c(x) of both components
-// from the populations that stream into x at this step.
-template <class L, class St, int LAYOUT>
-__global__ __launch_bounds__(512) void k_psi(StepParams p) {
-    using T = typename St::T;
-    using C = typename St::C;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;  // one row (segment) per workgroup
-    const int z = blockIdx.z;
-    if (x >= p.nx || y >= p.ny) return;
-    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
-    const uint32_t n = g.at(0, 0, 0);
-    const T *src = static_cast<const T *>(p.src);
-    C *psi = static_cast<C *>(const_cast<void *>(p.psi));
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-        const T *fc = src + size_t(c) * L::Q * p.S;
-        C r = C(0);
-#pragma unroll
-        for (int i = 0; i < L::Q; i++) {
-            int slot, dx, dy, dz;
-            canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            r += St::decode(LBM_LOAD(pop_addr(fc, p.S, slot, g, dx, dy, dz), i), C(L::w(i)));
-        }
-        const C rho = C(1) + r;
-        psi[size_t(c) * p.N + n] = p.psi_mode == 1 ? C(1) - exp(-rho) : rho;
-    }
-}
-
-// Two-component Shan-Chen step: both components in one pass (they share the common
-// velocity), equal relaxation times, EDM forcing.
-template <class L, class St, int LAYOUT>
-__global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
-    using T = typename St::T;
-    using C = typename St::C;
-    constexpr int Q = L::Q;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;  // one row (segment) per workgroup
-    const int z = blockIdx.z;
-    if (x >= p.nx || y >= p.ny) return;
-    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
-    const uint32_t n = g.at(0, 0, 0);
-    const uint32_t N = p.N, S = p.S;
-    const T *src = static_cast<const T *>(p.src);
-    T *dst = static_cast<T *>(p.dst);
-    const C *__restrict__ psi = static_cast<const C *>(p.psi);
-
-    C h[2][Q];
-    Macro<C> m[2];
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            int slot, dx, dy, dz;
-            canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            h[c][i] = St::decode(LBM_LOAD(pop_addr(src, S, c * Q + slot, g, dx, dy, dz), i), C(L::w(i)));
-        }
-        m[c] = moments<L, C>(h[c]);
-    }
-    // interaction forces: F_c = -G psi_c(x) sum_i w_i psi_other(x + e_i) e_i + rho_c g
-    C F[2][3];
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-        const C *po = psi + size_t(1 - c) * N;
-        C sx = C(0), sy = C(0), sz = C(0);
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            const C v = C(L::w(i)) * po[g.at(L::ex(i), L::ey(i), L::ez(i))];
-            sx += C(L::ex(i)) * v;
-            sy += C(L::ey(i)) * v;
-            sz += C(L::ez(i)) * v;
-        }
-        const C a = -C(p.G) * psi[size_t(c) * N + n];
-        F[c][0] = a * sx + m[c].rho * C(p.g[0]);
-        F[c][1] = a * sy + m[c].rho * C(p.g[1]);
-        F[c][2] = a * sz + m[c].rho * C(L::D == 3 ? p.g[2] : 0.0);
-    }
-    const C irs = C(1) / (m[0].rho + m[1].rho);
-    const C ux = (m[0].jx + m[1].jx) * irs, uy = (m[0].jy + m[1].jy) * irs, uz = (m[0].jz + m[1].jz) * irs;
-    const C usq15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
-    const C omega = C(p.omega);
-    bool bad = false;
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-        const C ir = C(1) / m[c].rho;
-        const C dx = F[c][0] * ir, dy = F[c][1] * ir, dz = F[c][2] * ir;
-        // feq(rho, u + du) - feq(rho, u) expanded so that it carries no cancellation
-        const C du15 = C(1.5) * (dx * (C(2) * ux + dx) + dy * (C(2) * uy + dy) + dz * (C(2) * uz + dz));
-        C o[Q];
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const C w = C(L::w(i));
-            const C eu = C(L::ex(i)) * ux + C(L::ey(i)) * uy + C(L::ez(i)) * uz;
-            const C ed = C(L::ex(i)) * dx + C(L::ey(i)) * dy + C(L::ez(i)) * dz;
-            const C heq = w * (m[c].drho + m[c].rho * (C(3) * eu + C(4.5) * eu * eu - usq15));
-            const C edm = w * m[c].rho * (C(3) * ed + C(4.5) * ed * (C(2) * eu + ed) - du15);
-            o[i] = h[c][i] + omega * (heq - h[c][i]) + edm;
-        }
-        // component momentum after relaxation towards rho_c u' plus the EDM kick F_c
-        conserve<L, C>(o, m[c].drho, m[c].jx + omega * (m[c].rho * ux - m[c].jx) + F[c][0],
-                       m[c].jy + omega * (m[c].rho * uy - m[c].jy) + F[c][1],
-                       m[c].jz + omega * (m[c].rho * uz - m[c].jz) + F[c][2]);
-        bad = bad || nonfinite<C>(o[0]);
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            int slot, dx, dy, dz;
-            post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            LBM_STORE_POP(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), 0u), i);
-        }
-    }
-    raise_divergence(p, bad);
 }
 
 // Launches k_step<MODEL> for every lattice, storage (with the stochastic-rounding

@@ -1,6 +1,6 @@
 // Step-kernel instantiations for the entropic collision (round-to-nearest storages).
 #include "dispatch.hpp"
-#include "step.hpp"
+#include "step_elbm.hpp"
 
 namespace lbm {
 

@@ -1,6 +1,6 @@
 // Two-component Shan-Chen kernels: the pseudopotential pre-pass and the step.
 #include "dispatch.hpp"
-#include "step.hpp"
+#include "step_sc.hpp"
 
 namespace lbm {
 

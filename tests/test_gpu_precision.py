@@ -42,3 +42,39 @@ def test_single_precision_findings():
     assert d["f32s"][0.0005] < 0.1 * d["f32"][0.0005]
     # double precision: the error rises with u0 at the top of the range (O(Ma^2) terms)
     assert v["f64"][0.1] > v["f64"][0.05]
+
+
+def test_half_precision_findings():
+    """The same study for the 16-bit shifted storages, with and without stochastic rounding
+    (FP32 arithmetic).  Measured at 128^2 (velocity relative L2 at u0 = 0.0005, 0.005, 0.05,
+    0.1): BF16 0.65, 0.094, 0.018, 0.010; BF16 with stochastic rounding 0.12, 0.031, 0.012,
+    0.0072; F16 0.034, 0.0053, 0.0014, 0.0031; F16 with stochastic rounding 0.028, 0.0042,
+    0.0015, 0.0033; FP64 4.0e-4, 4.0e-4, 8.6e-4, 3.0e-3.  The bounds are about twice these."""
+    import torch
+    b = _bench()
+    runs = [("f64", P.LBM_F64, 0), ("bf16s", P.LBM_BF16S, 0), ("bf16s_sr", P.LBM_BF16S, 1),
+            ("f16s", P.LBM_F16S, 0), ("f16s_sr", P.LBM_F16S, 1)]
+    u0s = (0.0005, 0.005, 0.05, 0.1)
+    res = b.precision_sweep(P, S, torch.cuda.Stream(), n=128, u0s=u0s, runs=runs)
+    v = {k: {r["u0"]: r["vel_rel_l2"] for r in rows} for k, rows in res.items()}
+    print(v)
+    # BF16 keeps 8 mantissa bits of f - w: at the lowest speed the per-step change of the
+    # decaying vortex falls below half an ulp and round-to-nearest loses most of the flow
+    assert 0.3 < v["bf16s"][0.0005] < 1.0
+    # stochastic rounding keeps those changes in expectation: a third or less of the error
+    assert v["bf16s_sr"][0.0005] < v["bf16s"][0.0005] / 3
+    # F16's 11 bits: ten times better than BF16 at the lowest speed
+    assert v["f16s"][0.0005] < v["bf16s"][0.0005] / 10
+    # the 16-bit errors fall as the flow speeds up (the changes grow against the ulp)
+    for k in ("bf16s", "bf16s_sr"):
+        assert v[k][0.0005] > v[k][0.005] > v[k][0.05] > v[k][0.1], k
+    for k in ("f16s", "f16s_sr"):
+        assert v[k][0.0005] > v[k][0.005] > v[k][0.05], k
+    # at the top speed F16 is at the double-precision (O(Ma^2)) error
+    for k in ("f16s", "f16s_sr"):
+        assert abs(v[k][0.1] - v["f64"][0.1]) < 0.2 * v["f64"][0.1], k
+    bounds = {"bf16s": (1.0, 0.19, 0.036, 0.021), "bf16s_sr": (0.25, 0.065, 0.024, 0.015),
+              "f16s": (0.07, 0.011, 0.003, 0.0062), "f16s_sr": (0.056, 0.0085, 0.003, 0.0066)}
+    for k, bs in bounds.items():
+        for u0, bound in zip(u0s, bs):
+            assert v[k][u0] <= bound, (k, u0, v[k][u0])
