@@ -121,6 +121,37 @@ def entropic_profile(P, S, stream, torch, steps, warmup, alpha_init=1):
             "warmup_nonconverged": int(nonconv)}
 
 
+def duct_profile(P, S, stream, torch, steps, warmup, storage, sr):
+    """The MRT duct 128x128x512 step alone (AB, with its four walls and body force), for
+    kernel traces and counter passes: `warmup` steps, then `steps` timed steps."""
+    c3 = S.c3_duct(128, 128, 512, steps=5000)
+    st = {"f32": P.LBM_F32, "bf16s": P.LBM_BF16S, "f16s": P.LBM_F16S}[storage]
+    s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
+    s.step(warmup)
+    ms = _time_steps(s, stream, torch, steps)
+    s.close()
+    b = bytes_per_node(st) + 1
+    return {"workload": "D3Q19 MRT duct 128x128x512, AB, %s storage%s" % (storage, ", stochastic rounding" if sr else ""),
+            "nodes": c3.n, "warmup": warmup, "steps": steps, "mlups": round(c3.n / ms / 1e3, 1),
+            "ms_per_step": round(ms, 4), "hbm_gbs_algorithmic": round(b * c3.n / (ms * 1e-3) / 1e9, 1)}
+
+
+def sc_profile(P, S, stream, torch, steps, warmup):
+    """The two-component Shan-Chen 384^3 step alone (FP32 storage), AA and then AB, for
+    kernel traces and counter passes: `warmup` steps, then `steps` timed steps each."""
+    c5 = S.c5_shan_chen(n=384)
+    out = {"workload": "D3Q19 two-component Shan-Chen 384^3, G=0.9, psi=rho, FP32 storage", "nodes": c5.n,
+           "warmup": warmup, "steps": steps}
+    for lay, name in ((P.LBM_AA, "aa"), (P.LBM_AB, "ab")):
+        s = P.Sim.from_case(c5, P.LBM_F32, lay, stream=stream)
+        s.step(warmup)
+        ms = _time_steps(s, stream, torch, steps)
+        s.close()
+        out[name] = {"mlups": round(c5.n / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                     "hbm_gbs_algorithmic": round(472 * c5.n / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
 def elbm_regimes(P, S, stream, torch):
     """D3Q19 entropic LBM 256^3 (u0 0.05, nu 1e-5), run to 8000 steps with Newton from the
     series estimate: (state, alpha) pairs every 500 steps, the network trained on 90% of
@@ -187,9 +218,11 @@ def elbm_regimes(P, S, stream, torch):
                           "mean_newton_iters": round(float((k * hist).sum() / max(hist.sum(), 1)), 4),
                           "newton_hist": [int(v) for v in hist[:8]], "nonconverged": int(nonconv),
                           "vel_rel_l2_vs_newton_from_2": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))}
-            rec = stored_valu("d3q19_elbm_f32_ab_256", "step_elbm.hip") if init == 1 and step_no == 1000 else None
+            tag = {1: "d3q19_elbm_f32_ab_256", 2: "d3q19_elbm_mlp_f32_ab_256"}.get(init)
+            rec = stored_valu(tag, "step_elbm.hip") if tag and step_no == 1000 else None
             if rec:
-                # VALU-issue roofline from the counted SIMD-cycles per node (series guess)
+                # VALU-issue roofline from the SIMD-cycles per node counted at step 1000 of the
+                # same vortex (series guess; the network's instruction mix for its row)
                 ach = rec["simd_cycles_per_node"] * c4.n / (ms * 1e-3)
                 rows[name]["roofline"] = {"bound": "alu", "achieved": round(ach / 1e12, 4),
                                           "peak": round(VALU_ISSUE_PEAK / 1e12, 4),
@@ -210,7 +243,8 @@ def run_extras(P, S, stream, torch):
     for st, sr in [(P.LBM_F64, 0), (P.LBM_F32, 0), (P.LBM_F32S, 0), (P.LBM_BF16S, 0), (P.LBM_BF16S, 1),
                    (P.LBM_F16S, 0), (P.LBM_F16S, 1)]:
         s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
-        ms = _time_steps(s, stream, torch, 200)
+        s.step(VARIANT_WARMUP)  # past the clock's ramp after the host-side set-up
+        ms = _time_steps(s, stream, torch, VARIANT_STEPS)
         s.close()
         s = P.Sim.from_case(c3, st, P.LBM_AB, sr, stream=stream)
         s.step(c3.steps)
@@ -402,9 +436,14 @@ def main():
     ap.add_argument("--precision-sweep", action="store_true",
                     help="run only the D2Q9 Taylor-Green precision study over u0 and storages (JSON line)")
     ap.add_argument("--entropic-profile", action="store_true",
-                    help="run only the entropic 256^3 step (series guess), for traces and counters (JSON line)")
+                    help="run only the entropic 256^3 step (first guess from --alpha-init), for traces and counters (JSON line)")
     ap.add_argument("--alpha-init", type=int, default=1, choices=[0, 1, 2],
                     help="first guess of the alpha solve for --entropic-profile (0: 2, 1: series, 2: network)")
+    ap.add_argument("--duct-profile", choices=["f32", "bf16s", "f16s"],
+                    help="run only the MRT duct 128x128x512 step in this storage, for traces and counters (JSON line)")
+    ap.add_argument("--sr", type=int, default=0, choices=[0, 1], help="stochastic rounding for --duct-profile")
+    ap.add_argument("--sc-profile", action="store_true",
+                    help="run only the Shan-Chen 384^3 step, AA then AB, for traces and counters (JSON line)")
     ap.add_argument("--elbm-regimes", action="store_true",
                     help="run only the entropic 256^3 vortex to 8000 steps: MLP training and the first guesses "
                          "timed at steps 1000 and 8000 (JSON line)")
@@ -431,6 +470,12 @@ def main():
         return
     if args.entropic_profile:
         print(json.dumps(entropic_profile(P, S, stream, torch, args.steps, args.warmup, args.alpha_init)))
+        return
+    if args.duct_profile:
+        print(json.dumps(duct_profile(P, S, stream, torch, args.steps, args.warmup, args.duct_profile, args.sr)))
+        return
+    if args.sc_profile:
+        print(json.dumps(sc_profile(P, S, stream, torch, args.steps, args.warmup)))
         return
     if args.elbm_regimes:
         print(json.dumps(elbm_regimes(P, S, stream, torch)))

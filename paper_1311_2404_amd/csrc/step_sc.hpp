@@ -8,11 +8,28 @@
 
 namespace lbm {
 
-// Shan-Chen pre-pass (the paper's macroscopic-field kernel): psi_c(x) of both components
-// from the populations that stream into x at this step.
+// psi_c(x) of component c from the populations that stream into node x at this step
+// (the pseudopotential of the multicomponent-models subsection: psi = rho, or 1 - exp(-rho)).
+template <class L, class St, int LAYOUT>
+__device__ __forceinline__ typename St::C psi_node(const StepParams &p, const Geo &g, int c) {
+    using T = typename St::T;
+    using C = typename St::C;
+    const T *fc = static_cast<const T *>(p.src) + size_t(c) * L::Q * p.S;
+    C r = C(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        int slot, dx, dy, dz;
+        canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+        r += St::decode(LBM_LOAD(pop_addr(fc, p.S, slot, g, dx, dy, dz), i), C(L::w(i)));
+    }
+    const C rho = C(1) + r;
+    return p.psi_mode == 1 ? C(1) - exp(-rho) : rho;
+}
+
+// Shan-Chen pre-pass (the paper's macroscopic-field kernel): psi of both components at
+// every node, for the two-kernel step.
 template <class L, class St, int LAYOUT>
 __global__ __launch_bounds__(512) void k_psi(StepParams p) {
-    using T = typename St::T;
     using C = typename St::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;  // one row (segment) per workgroup
@@ -20,40 +37,22 @@ __global__ __launch_bounds__(512) void k_psi(StepParams p) {
     if (x >= p.nx || y >= p.ny) return;
     const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     const uint32_t n = g.at(0, 0, 0);
-    const T *src = static_cast<const T *>(p.src);
     C *psi = static_cast<C *>(const_cast<void *>(p.psi));
 #pragma unroll
-    for (int c = 0; c < 2; c++) {
-        const T *fc = src + size_t(c) * L::Q * p.S;
-        C r = C(0);
-#pragma unroll
-        for (int i = 0; i < L::Q; i++) {
-            int slot, dx, dy, dz;
-            canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            r += St::decode(LBM_LOAD(pop_addr(fc, p.S, slot, g, dx, dy, dz), i), C(L::w(i)));
-        }
-        const C rho = C(1) + r;
-        psi[size_t(c) * p.N + n] = p.psi_mode == 1 ? C(1) - exp(-rho) : rho;
-    }
+    for (int c = 0; c < 2; c++) psi[size_t(c) * p.N + n] = psi_node<L, St, LAYOUT>(p, g, c);
 }
 
-// Two-component Shan-Chen step: both components in one pass (they share the common
-// velocity), equal relaxation times, EDM forcing.
-template <class L, class St, int LAYOUT>
-__global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
+// One node of the two-component Shan-Chen step: both components in one pass (they share
+// the common velocity), equal relaxation times, EDM forcing.  psi_at(c, dx, dy, dz) gives
+// psi_c at the node x + (dx, dy, dz).  Returns whether the node's result is non-finite.
+template <class L, class St, int LAYOUT, class PsiAt>
+__device__ __forceinline__ bool sc_node(const StepParams &p, const Geo &g, PsiAt psi_at) {
     using T = typename St::T;
     using C = typename St::C;
     constexpr int Q = L::Q;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;  // one row (segment) per workgroup
-    const int z = blockIdx.z;
-    if (x >= p.nx || y >= p.ny) return;
-    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
-    const uint32_t n = g.at(0, 0, 0);
-    const uint32_t N = p.N, S = p.S;
+    const uint32_t S = p.S;
     const T *src = static_cast<const T *>(p.src);
     T *dst = static_cast<T *>(p.dst);
-    const C *__restrict__ psi = static_cast<const C *>(p.psi);
 
     C h[2][Q];
     Macro<C> m[2];
@@ -71,16 +70,15 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
     C F[2][3];
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-        const C *po = psi + size_t(1 - c) * N;
         C sx = C(0), sy = C(0), sz = C(0);
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            const C v = C(L::w(i)) * po[g.at(L::ex(i), L::ey(i), L::ez(i))];
+            const C v = C(L::w(i)) * psi_at(1 - c, L::ex(i), L::ey(i), L::ez(i));
             sx += C(L::ex(i)) * v;
             sy += C(L::ey(i)) * v;
             sz += C(L::ez(i)) * v;
         }
-        const C a = -C(p.G) * psi[size_t(c) * N + n];
+        const C a = -C(p.G) * psi_at(c, 0, 0, 0);
         F[c][0] = a * sx + m[c].rho * C(p.g[0]);
         F[c][1] = a * sy + m[c].rho * C(p.g[1]);
         F[c][2] = a * sz + m[c].rho * C(L::D == 3 ? p.g[2] : 0.0);
@@ -118,6 +116,23 @@ __global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
             LBM_STORE_POP(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), 0u), i);
         }
     }
+    return bad;
+}
+
+// The two-kernel step, after k_psi: one thread per node, psi read from the pre-pass array.
+template <class L, class St, int LAYOUT>
+__global__ __launch_bounds__(512) void k_step_sc(StepParams p) {
+    using C = typename St::C;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;  // one row (segment) per workgroup
+    const int z = blockIdx.z;
+    if (x >= p.nx || y >= p.ny) return;
+    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+    const C *__restrict__ psi = static_cast<const C *>(p.psi);
+    const uint32_t N = p.N;
+    const bool bad = sc_node<L, St, LAYOUT>(p, g, [&](int c, int dx, int dy, int dz) {
+        return psi[size_t(c) * N + g.at(dx, dy, dz)];
+    });
     raise_divergence(p, bad);
 }
 
