@@ -147,9 +147,20 @@ StepParams base_params(const lbm_sim *s) {
     p.tyl = s->tyl;
     p.flags = s->has_walls ? s->flags_d : nullptr;
     p.omega = 1.0 / s->tau;
-    for (int a = 0; a < 3; a++) p.g[a] = s->g[a];
+    for (int a = 0; a < 3; a++) {
+        p.g[a] = s->g[a];
+        p.g_f[a] = float(s->g[a]);
+    }
     p.has_force = (s->g[0] != 0.0 || s->g[1] != 0.0 || s->g[2] != 0.0) ? 1 : 0;
-    for (int k = 0; k < 19; k++) p.s[k] = s->s[k];
+    for (int k = 0; k < s->Q; k++) {
+        const double n2 = s->lattice == LBM_D3Q19 ? D3Q19::mrt_n2(k) : D2Q9::mrt_n2(k);
+        const bool conserved = k == 0 || k == 3 || k == 5 || (k == 7 && s->lattice == LBM_D3Q19);
+        const double sk = s->s[k];
+        p.mrt[0][k] = conserved ? 1.0 / n2 : (1.0 - sk) / n2;
+        p.mrt[1][k] = conserved ? 0.0 : sk / n2;
+        p.mrt[2][k] = conserved ? 0.0 : (1.0 - 0.5 * sk) / n2;
+        for (int j = 0; j < 3; j++) p.mrt_f[j][k] = float(p.mrt[j][k]);
+    }
     for (int a = 0; a < 3; a++) p.u_bc[a] = s->u_bc[a];
     p.tau0 = s->tau;
     p.tau_a = s->tau;

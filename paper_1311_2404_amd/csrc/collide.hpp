@@ -26,6 +26,31 @@ struct Macro {
     C drho, rho, jx, jy, jz;
 };
 
+// 1/x in the compute type: FP64 divides; FP32 takes the hardware reciprocal (1 ulp)
+// refined by one Newton step (within an ulp of the quotient), about a third of the
+// instructions of the correctly rounded division.
+template <class C>
+__device__ __forceinline__ C inv(C x) {
+    if constexpr (sizeof(C) == 8) {
+        return C(1) / x;
+    } else {
+        const float r = __builtin_amdgcn_rcpf(x);
+        return fmaf(fmaf(-x, r, 1.0f), r, r);
+    }
+}
+
+// Step parameters in the compute type (the FP32 copies spare a conversion per wave).
+template <class C>
+__device__ __forceinline__ C body_g(const StepParams &p, int a) {
+    if constexpr (sizeof(C) == 8) return p.g[a];
+    else return p.g_f[a];
+}
+template <class C>
+__device__ __forceinline__ C mrt_coef(const StepParams &p, int j, int k) {
+    if constexpr (sizeof(C) == 8) return p.mrt[j][k];
+    else return p.mrt_f[j][k];
+}
+
 template <class L, class C>
 __device__ __forceinline__ Macro<C> moments(const C *h) {
     Macro<C> m;
@@ -104,11 +129,11 @@ template <class L, class C, bool FORCE>
 __device__ __forceinline__ void collide_bgk_body(const C *h, C *o, const StepParams &p) {
     const Macro<C> m = moments<L, C>(h);
     const C omega = C(p.omega);
-    const C irho = C(1) / m.rho;
+    const C irho = inv<C>(m.rho);
     C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
     C Fx = C(0), Fy = C(0), Fz = C(0);
     if constexpr (FORCE) {
-        const C gx = C(p.g[0]), gy = C(p.g[1]), gz = C(L::D == 3 ? p.g[2] : 0.0);
+        const C gx = body_g<C>(p, 0), gy = body_g<C>(p, 1), gz = L::D == 3 ? body_g<C>(p, 2) : C(0);
         vx += C(0.5) * gx;
         vy += C(0.5) * gy;
         vz += C(0.5) * gz;
@@ -172,7 +197,7 @@ __device__ __forceinline__ void neq_moments_add(NeqMoments<C> &q, int i, C fn) {
 template <class L, class C>
 __device__ __forceinline__ void collide_reg(const C *h, C *o, const StepParams &p) {
     const Macro<C> m = moments<L, C>(h);
-    const C irho = C(1) / m.rho;
+    const C irho = inv<C>(m.rho);
     const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
     const C usq15 = C(1.5) * (vx * vx + vy * vy + vz * vz);
     C heq[L::Q];
@@ -209,11 +234,11 @@ __device__ __forceinline__ void collide_reg(const C *h, C *o, const StepParams &
 template <class L, class C, bool FORCE>
 __device__ __forceinline__ void collide_smag_body(const C *h, C *o, const StepParams &p) {
     const Macro<C> m = moments<L, C>(h);
-    const C irho = C(1) / m.rho;
+    const C irho = inv<C>(m.rho);
     C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
     C Fx = C(0), Fy = C(0), Fz = C(0);
     if constexpr (FORCE) {
-        const C gx = C(p.g[0]), gy = C(p.g[1]), gz = C(L::D == 3 ? p.g[2] : 0.0);
+        const C gx = body_g<C>(p, 0), gy = body_g<C>(p, 1), gz = L::D == 3 ? body_g<C>(p, 2) : C(0);
         vx += C(0.5) * gx;
         vy += C(0.5) * gy;
         vz += C(0.5) * gz;
@@ -300,16 +325,17 @@ __device__ __forceinline__ void collide_mrt_d3q19(const C *h, C *o, const StepPa
     m[18] = d11 - d13 - d15 + d17;
 
     const C rho = C(1) + drho;
-    const C irho = C(1) / rho;
+    const C irho = inv<C>(rho);
     C vx = jx * irho, vy = jy * irho, vz = jz * irho;
     C Fx = C(0), Fy = C(0), Fz = C(0);
     if constexpr (FORCE) {
-        vx += C(0.5) * C(p.g[0]);
-        vy += C(0.5) * C(p.g[1]);
-        vz += C(0.5) * C(p.g[2]);
-        Fx = rho * C(p.g[0]);
-        Fy = rho * C(p.g[1]);
-        Fz = rho * C(p.g[2]);
+        const C gx = body_g<C>(p, 0), gy = body_g<C>(p, 1), gz = body_g<C>(p, 2);
+        vx += C(0.5) * gx;
+        vy += C(0.5) * gy;
+        vz += C(0.5) * gz;
+        Fx = rho * gx;
+        Fy = rho * gy;
+        Fz = rho * gz;
     }
     const C vsq = vx * vx + vy * vy + vz * vz;
     // equilibrium moments of the polynomial equilibrium at (rho, v), shifted space
@@ -343,23 +369,24 @@ __device__ __forceinline__ void collide_mrt_d3q19(const C *h, C *o, const StepPa
     mf[15] = vx * Fz + vz * Fx;
     mf[16] = mf[17] = mf[18] = C(0);
 
-    // relax; conserved rows: rho unchanged, j gains F whatever their rate
-    const C n2[19] = {C(19), C(2394), C(252), C(10), C(40), C(10), C(40), C(10), C(40), C(36),
-                      C(72), C(12), C(24), C(4), C(4), C(4), C(8), C(8), C(8)};
+    // relax, each row scaled by 1/|M_k|^2 for the inverse transform (coefficients from the
+    // host); conserved rows: rho unchanged, j gains F whatever their rate
     C a[19];
-    a[0] = drho / n2[0];
+    a[0] = drho * mrt_coef<C>(p, 0, 0);
     // momentum after the force's full step (no add of a zero force: -0 + 0 is +0)
     const C Jx = FORCE ? jx + Fx : jx, Jy = FORCE ? jy + Fy : jy, Jz = FORCE ? jz + Fz : jz;
-    a[3] = Jx / n2[3];
-    a[5] = Jy / n2[5];
-    a[7] = Jz / n2[7];
+    a[3] = Jx * mrt_coef<C>(p, 0, 3);
+    a[5] = Jy * mrt_coef<C>(p, 0, 5);
+    a[7] = Jz * mrt_coef<C>(p, 0, 7);
 #pragma unroll
     for (int k = 1; k < 19; k++) {
         if (k == 3 || k == 5 || k == 7) continue;
-        const C sk = C(p.s[k]);
-        C r = m[k] - sk * (m[k] - meq[k]);
-        if constexpr (FORCE) r += (C(1) - C(0.5) * sk) * mf[k];
-        a[k] = r * (C(1) / n2[k]);
+        C r = mrt_coef<C>(p, 0, k) * m[k];
+        if (k < 16) {  // rows 16-18 have no equilibrium or source part
+            r += mrt_coef<C>(p, 1, k) * meq[k];
+            if constexpr (FORCE) r += mrt_coef<C>(p, 2, k) * mf[k];
+        }
+        a[k] = r;
     }
     // inverse transform M^T a, even/odd parts per opposite pair
     o[0] = a[0] - C(30) * a[1] + C(12) * a[2];
@@ -414,13 +441,14 @@ __device__ __forceinline__ void collide_mrt_d2q9(const C *h, C *o, const StepPar
     m[7] = s1 - s3;
     m[8] = s5 - s7;
     const C rho = C(1) + drho;
-    const C irho = C(1) / rho;
+    const C irho = inv<C>(rho);
     C vx = jx * irho, vy = jy * irho, Fx = C(0), Fy = C(0);
     if constexpr (FORCE) {
-        vx += C(0.5) * C(p.g[0]);
-        vy += C(0.5) * C(p.g[1]);
-        Fx = rho * C(p.g[0]);
-        Fy = rho * C(p.g[1]);
+        const C gx = body_g<C>(p, 0), gy = body_g<C>(p, 1);
+        vx += C(0.5) * gx;
+        vy += C(0.5) * gy;
+        Fx = rho * gx;
+        Fy = rho * gy;
     }
     const C vsq = vx * vx + vy * vy, vF = vx * Fx + vy * Fy;
     C meq[9], mf[9];
@@ -436,19 +464,17 @@ __device__ __forceinline__ void collide_mrt_d2q9(const C *h, C *o, const StepPar
     mf[6] = -Fy;
     mf[7] = C(2) * (vx * Fx - vy * Fy);
     mf[8] = vx * Fy + vy * Fx;
-    const C n2[9] = {C(9), C(36), C(36), C(6), C(12), C(6), C(12), C(4), C(4)};
     C a[9];
-    a[0] = drho / n2[0];
+    a[0] = drho * mrt_coef<C>(p, 0, 0);
     const C Jx = FORCE ? jx + Fx : jx, Jy = FORCE ? jy + Fy : jy;
-    a[3] = Jx / n2[3];
-    a[5] = Jy / n2[5];
+    a[3] = Jx * mrt_coef<C>(p, 0, 3);
+    a[5] = Jy * mrt_coef<C>(p, 0, 5);
 #pragma unroll
     for (int k = 1; k < 9; k++) {
         if (k == 3 || k == 5) continue;
-        const C sk = C(p.s[k]);
-        C r = m[k] - sk * (m[k] - meq[k]);
-        if constexpr (FORCE) r += (C(1) - C(0.5) * sk) * mf[k];
-        a[k] = r * (C(1) / n2[k]);
+        C r = mrt_coef<C>(p, 0, k) * m[k] + mrt_coef<C>(p, 1, k) * meq[k];
+        if constexpr (FORCE) r += mrt_coef<C>(p, 2, k) * mf[k];
+        a[k] = r;
     }
     o[0] = a[0] - C(4) * a[1] + C(4) * a[2];
     const C Eax = a[0] - a[1] - C(2) * a[2], Edg = a[0] + C(2) * a[1] + a[2];

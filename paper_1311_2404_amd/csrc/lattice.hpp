@@ -25,6 +25,11 @@ struct D2Q9 {
     __host__ __device__ static constexpr double w(int i) {
         return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
     }
+    // squared norms of the MRT basis rows (the rows are listed with the MRT collision)
+    __host__ __device__ static constexpr double mrt_n2(int k) {
+        constexpr double t[9] = {9, 36, 36, 6, 12, 6, 12, 4, 4};
+        return t[k];
+    }
 };
 
 struct D3Q19 {
@@ -44,6 +49,10 @@ struct D3Q19 {
     }
     __host__ __device__ static constexpr double w(int i) {
         return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+    __host__ __device__ static constexpr double mrt_n2(int k) {
+        constexpr double t[19] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
+        return t[k];
     }
 };
 

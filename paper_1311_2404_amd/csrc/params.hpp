@@ -30,8 +30,14 @@ struct StepParams {
     // physics
     double omega;               // 1/tau
     double g[3];                // body acceleration
+    float g_f[3];               // the same in FP32
     int has_force;
-    double s[19];               // MRT rates in moment order
+    // MRT relaxation with the basis row's squared norm |M_k|^2 folded in: the rescaled
+    // post-collision moment is a_k = mrt[0][k] m_k + mrt[1][k] meq_k + mrt[2][k] mF_k, the
+    // three being (1 - s_k), s_k and 1 - s_k/2 over |M_k|^2; for the conserved rows
+    // mrt[0][k] = 1/|M_k|^2 and the others are 0.  mrt_f holds the same in FP32.
+    double mrt[3][19];
+    float mrt_f[3][19];
     double u_bc[3];             // velocity of the equilibrium velocity nodes (flag 2)
     double tau_a, tau_b, tau_phi;  // free energy: f relaxation at phi = +1 / -1, g relaxation
     double fe_a, fe_kappa, fe_gamma;  // free energy: A, kappa, Gamma

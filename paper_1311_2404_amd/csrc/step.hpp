@@ -146,6 +146,28 @@ __device__ __forceinline__ void post_dir(int layout, int i, int &slot, int &dx, 
     }
 }
 
+// Store of population slot `slot` at node x + (dx, dy, dz): pop_addr and pop_store, except
+// for 2-byte elements.  Those go through a buffer descriptor built on the row's base (a
+// scalar: y and z are the same for the whole workgroup) with the lane's 32-bit byte
+// offset of x.  As plain stores the compiler chains the 19 addresses of a node into
+// 64-bit per-lane pointer increments, one VALU add per store, and the 16-bit steps are
+// bound by VALU issue.  The descriptor's fourth word is the gfx9 family's untyped-buffer
+// format; its record count only bounds the row offset (< 2^31 bytes).
+template <class L, int LAYOUT, class T>
+__device__ __forceinline__ void pop_store_at(T *base, uint32_t S, int slot, const Geo &g, int dx, int dy, int dz, T v,
+                                             int i) {
+    if constexpr (sizeof(T) == 2) {
+        T *row = base + (size_t(slot) * S + g.row_off(dy, dz));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, 0x7fffffff, 0x00020000);
+        const short sv = __builtin_bit_cast(short, v);
+        const int off = int(g.x_of(dx) * 2u);
+        if (LAYOUT == LAYOUT_AA_ODD && L::ex(i) != 0) __builtin_amdgcn_raw_buffer_store_b16(sv, rs, off, 0, 0);
+        else __builtin_amdgcn_raw_buffer_store_b16(sv, rs, off, 0, 2);  // non-temporal (the pop_store rule)
+    } else {
+        pop_store<L, LAYOUT>(pop_addr(base, S, slot, g, dx, dy, dz), v, i);
+    }
+}
+
 // Address of population slot `slot` at node x + (dx, dy, dz) in a copy.  In the step
 // kernels y and z are the same for the whole workgroup, so the slot and row part is a
 // scalar base.  For 2-byte elements the x part is added as a 32-bit byte offset, which
@@ -305,8 +327,8 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         for (int i = 0; i < Q; i++) {
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            if constexpr (LAYOUT == LAYOUT_AB) LBM_STORE(pop_addr(dst, S, slot, gs, 0, 0, 0), out[i]);
-            else LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), out[i], i);
+            if constexpr (LAYOUT == LAYOUT_AB) pop_store_at<L, LAYOUT>(dst, S, slot, gs, 0, 0, 0, out[i], i);
+            else pop_store_at<L, LAYOUT>(dst, S, slot, g, dx, dy, dz, out[i], i);
         }
         raise_divergence(p, bad);
     }

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(512) void k_step_elbm(StepParams p) {
         for (int i = 0; i < Q; i++) {
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), out[i], i);
+            pop_store_at<L, LAYOUT>(dst, S, slot, g, dx, dy, dz, out[i], i);
         }
         raise_divergence(p, bad);
     }

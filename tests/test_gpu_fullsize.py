@@ -194,13 +194,15 @@ def test_c3_fullsize_5000_steps_storage_errors():
     assert 4.5e-3 < ref[2].max() < 5.5e-3  # plug-flow core velocity ~ g t at 5000 steps
     err = {k: rel(v, ref) for k, v in u.items()}
     print({"%s_sr%d" % (P.STORAGE_NAMES[k[0]], k[1]): "%.3e" % v for k, v in err.items()})
-    # FP32 compute misses the 1e-5 target here (measured 4.7e-5 plain, 3.3e-5 shifted): the
-    # bounds are twice the measured errors, so a regression shows
+    # FP32 compute misses the 1e-5 target here (measured 4.6e-5 plain, 3.3e-5 shifted).  The
+    # bounds are about twice the measured errors, so a regression shows: BF16 with stochastic
+    # rounding 1.35e-3, F16 3.1e-3 to 4.0e-3 (round to nearest moves with the arithmetic's
+    # rounding order), F16 with stochastic rounding 1.77e-4
     assert err[(P.LBM_F32S, 0)] <= 7e-5, err
     assert err[(P.LBM_F32, 0)] <= 1e-4, err
-    assert err[(P.LBM_BF16S, 1)] <= 5e-2, err
-    assert err[(P.LBM_F16S, 0)] <= 5e-2, err
-    assert err[(P.LBM_F16S, 1)] <= 5e-2, err
+    assert err[(P.LBM_BF16S, 1)] <= 3e-3, err
+    assert err[(P.LBM_F16S, 0)] <= 8e-3, err
+    assert err[(P.LBM_F16S, 1)] <= 4e-4, err
 
 
 # ----------------------------------------------------------- C4: D3Q19 ELBM 256^3
