@@ -254,10 +254,11 @@ def run_extras(P, S, stream, torch):
         rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")] = {
             "mlups": round(c3.n / ms / 1e3, 1), "bytes_per_node": b,
             "hbm_gbs_algorithmic": round(b * c3.n / (ms * 1e-3) / 1e9, 1)}
-    ref = us[(P.LBM_F64, 0)]
+    ref, ref32 = us[(P.LBM_F64, 0)], us[(P.LBM_F32, 0)]
     for (st, sr), u in us.items():
-        rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")]["vel_rel_l2_vs_fp64"] = float(
-            np.linalg.norm(u - ref) / np.linalg.norm(ref))
+        row = rows[P.STORAGE_NAMES[st] + ("_sr" if sr else "")]
+        row["vel_rel_l2_vs_fp64"] = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+        row["vel_rel_l2_vs_f32"] = float(np.linalg.norm(u - ref32) / np.linalg.norm(ref32))
     out["d3q19_mrt_duct_128x128x512_5000_steps"] = rows
     print("[bench] MRT duct done", file=sys.stderr, flush=True)
 

@@ -211,7 +211,9 @@ __device__ __forceinline__ double alpha_D(const C *h, const C *heq, const AlphaN
 // 1/f in FP64: the hardware reciprocal (2^-23 relative) refined by Newton steps, each of
 // which doubles the correct bits: two for FP64 compute (full precision), one for FP32
 // compute (2^-46, far below what FP32 populations resolve).  About half the
-// instructions of a correctly rounded division.
+// instructions of a correctly rounded division.  The Newton updates of alpha take the
+// two-step form: an update's last-bit rounding is corrected by the next iterate or lies
+// far below the tolerance.
 template <class C = double>
 __device__ __forceinline__ double recip(double f) {
     double r = __builtin_amdgcn_rcp(f);
@@ -331,7 +333,7 @@ __device__ __forceinline__ void alpha_moments_k(const C *h, const C *heq, AlphaN
         }
     }
     // min over d_i < 0 of -1/d_i is 1 / max(-d_i)
-    s.amax = s.mneg > 0.0 ? 1.0 / s.mneg : INFINITY;
+    s.amax = s.mneg > 0.0 ? recip<double>(s.mneg) : INFINITY;
 }
 
 // the order of the wave, then its moments (after alpha_project)
@@ -380,7 +382,7 @@ __device__ __forceinline__ AlphaOut alpha_newton_log(const C *h, const C *heq, c
         // g at the rounding floor of its own sum: a is the root to working precision
         if (fabs(g) <= 64.0 * 2.220446049250313e-16 * gs) return {a, k, 1};
         if (g < 0.0) lo = a; else hi = a;
-        double an = a - g / dg;
+        double an = a - g * recip<double>(dg);
         if (fabs(an - a) <= tol) return {an, k, 1};
         if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
         a = an;
@@ -417,7 +419,7 @@ __device__ __forceinline__ AlphaOut alpha_newton_moments(const double *am, doubl
         // rounding floor of g: its two leading terms, a_2 x^2 / 2 and B x, cancel at the root
         if (fabs(g) <= 64.0 * 2.220446049250313e-16 * x * (fabs(c[2]) * x + fabs(B))) return {x, it, 1};
         if (g < 0.0) lo = x; else hi = x;
-        double xn = x - g / dg;
+        double xn = x - g * recip<double>(dg);
         if (fabs(xn - x) <= tol) return {xn, it, 1};
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
         x = xn;

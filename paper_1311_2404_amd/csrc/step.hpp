@@ -147,22 +147,37 @@ __device__ __forceinline__ void post_dir(int layout, int i, int &slot, int &dx, 
 }
 
 // Store of population slot `slot` at node x + (dx, dy, dz): pop_addr and pop_store, except
-// for 2-byte elements.  Those go through a buffer descriptor built on the row's base (a
-// scalar: y and z are the same for the whole workgroup) with the lane's 32-bit byte
-// offset of x.  As plain stores the compiler chains the 19 addresses of a node into
-// 64-bit per-lane pointer increments, one VALU add per store, and the 16-bit steps are
-// bound by VALU issue.  The descriptor's fourth word is the gfx9 family's untyped-buffer
-// format; its record count only bounds the row offset (< 2^31 bytes).
-template <class L, int LAYOUT, class T>
+// for 2-byte elements, and for every element size when BUF.  Those go through a buffer
+// descriptor built on the row's base (a scalar: y and z are the same for the whole
+// workgroup) with the lane's 32-bit byte offset of x.  As plain stores the compiler
+// chains the 19 addresses of a node into 64-bit per-lane pointer increments, one VALU
+// add per store, which costs the steps bound by VALU issue (the 16-bit steps, the
+// entropic step: BUF); the memory-bound 4- and 8-byte steps measured ~1% faster with
+// the per-lane 64-bit addresses.  The descriptor's fourth word is the gfx9 family's
+// untyped-buffer format; its record count only bounds the row offset (< 2^31 bytes).
+template <class L, int LAYOUT, bool BUF = false, class T>
 __device__ __forceinline__ void pop_store_at(T *base, uint32_t S, int slot, const Geo &g, int dx, int dy, int dz, T v,
                                              int i) {
-    if constexpr (sizeof(T) == 2) {
+    if constexpr (sizeof(T) == 2 || BUF) {
         T *row = base + (size_t(slot) * S + g.row_off(dy, dz));
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, 0x7fffffff, 0x00020000);
-        const short sv = __builtin_bit_cast(short, v);
-        const int off = int(g.x_of(dx) * 2u);
-        if (LAYOUT == LAYOUT_AA_ODD && L::ex(i) != 0) __builtin_amdgcn_raw_buffer_store_b16(sv, rs, off, 0, 0);
-        else __builtin_amdgcn_raw_buffer_store_b16(sv, rs, off, 0, 2);  // non-temporal (the pop_store rule)
+        const int off = int(g.x_of(dx) * uint32_t(sizeof(T)));
+        // non-temporal (aux 2) except where pop_store leaves the hint off
+        const bool plain = LAYOUT == LAYOUT_AA_ODD && L::ex(i) != 0;
+        if constexpr (sizeof(T) == 2) {
+            const short sv = __builtin_bit_cast(short, v);
+            if (plain) __builtin_amdgcn_raw_buffer_store_b16(sv, rs, off, 0, 0);
+            else __builtin_amdgcn_raw_buffer_store_b16(sv, rs, off, 0, 2);
+        } else if constexpr (sizeof(T) == 4) {
+            const int sv = __builtin_bit_cast(int, v);
+            if (plain) __builtin_amdgcn_raw_buffer_store_b32(sv, rs, off, 0, 0);
+            else __builtin_amdgcn_raw_buffer_store_b32(sv, rs, off, 0, 2);
+        } else {
+            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+            const u32x2 sv = __builtin_bit_cast(u32x2, v);
+            if (plain) __builtin_amdgcn_raw_buffer_store_b64(sv, rs, off, 0, 0);
+            else __builtin_amdgcn_raw_buffer_store_b64(sv, rs, off, 0, 2);
+        }
     } else {
         pop_store<L, LAYOUT>(pop_addr(base, S, slot, g, dx, dy, dz), v, i);
     }

@@ -54,7 +54,7 @@ __device__ __forceinline__ void alpha_newton_log_queued(AlphaLogQueue<Q> &sq, in
             return;
         }
         if (g < 0.0) lo = a; else hi = a;
-        double an = a - g / dg;
+        double an = a - g * recip<double>(dg);
         if (fabs(an - a) <= tol) {
             sq.alpha[e] = an, sq.iters[e] = k, sq.conv[e] = 1;
             return;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(512) void k_step_elbm(StepParams p) {
 #pragma unroll
     for (int i = 0; i < Q; i++) h[i] = St::decode(raw[i], C(L::w(i)));
     const Macro<C> m = moments<L, C>(h);
-    const C irho = C(1) / m.rho;
+    const C irho = inv<C>(m.rho);
     const C vx = m.jx * irho, vy = m.jy * irho, vz = m.jz * irho;
     C heq[Q];
     entropic_heq<L, C>(m.drho, m.rho, vx, vy, vz, heq);
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(512) void k_step_elbm(StepParams p) {
         for (int i = 0; i < Q; i++) {
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            pop_store_at<L, LAYOUT>(dst, S, slot, g, dx, dy, dz, out[i], i);
+            pop_store_at<L, LAYOUT, true>(dst, S, slot, g, dx, dy, dz, out[i], i);
         }
         raise_divergence(p, bad);
     }
