@@ -152,8 +152,10 @@ __device__ __forceinline__ void post_dir(int layout, int i, int &slot, int &dx, 
 // workgroup) with the lane's 32-bit byte offset of x.  As plain stores the compiler
 // chains the 19 addresses of a node into 64-bit per-lane pointer increments, one VALU
 // add per store, which costs the steps bound by VALU issue (the 16-bit steps, the
-// entropic step: BUF); the memory-bound 4- and 8-byte steps measured ~1% faster with
-// the per-lane 64-bit addresses.  The descriptor's fourth word is the gfx9 family's
+// entropic step: BUF) and registers where many addresses are live (the Shan-Chen
+// step).  The memory-bound 4- and 8-byte LBGK/MRT steps keep the per-lane 64-bit
+// addresses: ~1% faster, in AA odd too, where the buffer form cut 93 VGPRs to 58 and
+// still ran 0.6% slower.  The descriptor's fourth word is the gfx9 family's
 // untyped-buffer format; its record count only bounds the row offset (< 2^31 bytes).
 template <class L, int LAYOUT, bool BUF = false, class T>
 __device__ __forceinline__ void pop_store_at(T *base, uint32_t S, int slot, const Geo &g, int dx, int dy, int dz, T v,

@@ -183,8 +183,9 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
     for (int i = 0; i < Q; i++) {
         int slot, dx, dy, dz;
         post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        LBM_STORE_POP(pop_addr(dst, S, slot, g, dx, dy, dz), of[i], i);
-        LBM_STORE_POP(pop_addr(dst, S, Q + slot, g, dx, dy, dz), og[i], i);
+        // buffer-descriptor stores in AB (+0.9% on the spinodal case; AA measured 0.6% slower)
+        pop_store_at<L, LAYOUT, LAYOUT == LAYOUT_AB>(dst, S, slot, g, dx, dy, dz, of[i], i);
+        pop_store_at<L, LAYOUT, LAYOUT == LAYOUT_AB>(dst, S, Q + slot, g, dx, dy, dz, og[i], i);
     }
     raise_divergence(p, bad);
 }

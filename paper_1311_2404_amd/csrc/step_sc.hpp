@@ -113,7 +113,9 @@ __device__ __forceinline__ bool sc_node(const StepParams &p, const Geo &g, PsiAt
         for (int i = 0; i < Q; i++) {
             int slot, dx, dy, dz;
             post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-            LBM_STORE_POP(pop_addr(dst, S, c * Q + slot, g, dx, dy, dz), St::encode(o[i], C(L::w(i)), 0u), i);
+            // buffer-descriptor stores: 146 -> 111 VGPRs in the AA odd step (3 -> 4 waves/SIMD,
+            // +3.5% on the AA run at 384^3), AB unchanged
+            pop_store_at<L, LAYOUT, true>(dst, S, c * Q + slot, g, dx, dy, dz, St::encode(o[i], C(L::w(i)), 0u), i);
         }
     }
     return bad;
