@@ -262,6 +262,42 @@ def test_aa_equals_ab_bitwise(storage, steps):
     assert np.array_equal(fa, fb) and np.array_equal(ua, ub)
 
 
+def _xstage_case(lattice, model):
+    """Rows of 256 nodes: one workgroup per row, so the AB and AA odd steps move the
+    x-moving populations through LDS (aligned loads, and in AA odd aligned stores, with the
+    one-node shift in LDS)."""
+    shape = (256, 9, 1) if lattice == S.D2Q9 else (256, 6, 4)
+    g = (2e-5, -1e-5, 3e-5 if lattice == S.D3Q19 else 0.0)
+    kw = dict(force=g, walls=True, tau=0.6)
+    if model == S.MRT:
+        kw["mrt_rates"] = (S.mrt_rates_d2q9 if lattice == S.D2Q9 else S.mrt_rates_d3q19)(1 / 0.6, 1.2)
+    elif model == S.REG:
+        kw = dict(walls=True, tau=0.55)
+    elif model == S.SMAG:
+        kw.update(tau=0.52, cs_smag=0.2)
+    return random_case(lattice, model, *shape, **kw)
+
+
+@pytest.mark.parametrize("model", [S.BGK, S.MRT, S.REG, S.SMAG])
+@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
+def test_x_staging_fp64(lattice, model):
+    check_f64(_xstage_case(lattice, model), 9)
+
+
+@pytest.mark.parametrize("storage,sr", [(P.LBM_F64, 0), (P.LBM_F32, 0), (P.LBM_F32S, 0), (P.LBM_BF16S, 1),
+                                        (P.LBM_F16S, 0)])
+@pytest.mark.parametrize("model", [S.BGK, S.MRT, S.SMAG])
+def test_x_staging_bitwise(model, storage, sr):
+    """The staged AB and AA odd steps give the same bits: walls and force, after odd and
+    even step counts, on both lattices."""
+    for lattice in (S.D2Q9, S.D3Q19):
+        c = _xstage_case(lattice, model)
+        for steps in (1, 6, 7):
+            fa, ra, ua = gpu_run(c, steps, storage, P.LBM_AB, sr)
+            fb, rb, ub = gpu_run(c, steps, storage, P.LBM_AA, sr)
+            assert np.array_equal(fa, fb) and np.array_equal(ua, ub) and np.array_equal(ra, rb), (lattice, steps)
+
+
 _POP_LAYOUTS = [
     dict(kind=P.LBM_POP_SOA),
     dict(kind=P.LBM_POP_SOA, soa_pad=0),
