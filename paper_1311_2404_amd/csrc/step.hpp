@@ -282,7 +282,7 @@ __host__ __device__ constexpr int xmove_count() {
 // FLAGS: 0 no node flags, 1 fluid and wall nodes, 2 also boundary nodes (equilibrium
 // velocity and half-way bounce-back; their paths are compiled only where they exist).
 //
-// XSTAGE (AB and AA odd steps, one whole x row per workgroup): the populations that move
+// XSTAGE (AB and AA odd steps, whole x rows per workgroup): the populations that move
 // along x are read, and in AA odd also written, on aligned segments, and the one-node
 // shift along x goes through LDS, as in the paper's step algorithm.  Lane x loads the
 // slot it pulls from (AB: i, AA odd: opp(i)) at its own x of the source row into LDS;
@@ -331,8 +331,12 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         const T *src = static_cast<const T *>(p.src);
         T *dst = static_cast<T *>(p.dst);
         T raw[Q];
+        // LDS of the x staging: per row of the workgroup, the x-moving values read (xin) and,
+        // in AA odd, written (xout)
         [[maybe_unused]] extern __shared__ unsigned char lds_x[];
-        [[maybe_unused]] T *xin = reinterpret_cast<T *>(lds_x);
+        [[maybe_unused]] const int rows_lds = LAYOUT == LAYOUT_AA_ODD ? 2 : 1;
+        [[maybe_unused]] T *xin = reinterpret_cast<T *>(lds_x) +
+                                  size_t(MULTI_ROW ? threadIdx.y : 0) * rows_lds * xmove_count<L>() * p.nx;
         [[maybe_unused]] T *xout = xin + xmove_count<L>() * p.nx;
         if constexpr (XSTAGE) {
 #pragma unroll
@@ -430,14 +434,14 @@ hipError_t launch_k_step(int lattice, int storage, int sr, int layout, int flags
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
-                // the AB and AA odd steps stage their x shifts in LDS where a workgroup is one
-                // whole row (no padding lanes)
-                const bool xstage = int(c.block.x) == p.nx && c.block.y == 1 && c.grid.x == 1 &&
-                                    p.nx % 64 == 0 && p.nx <= 512;
+                // the AB and AA odd steps stage their x shifts in LDS where a workgroup is whole
+                // rows (no padding lanes, every row of every workgroup inside the lattice)
+                const bool xstage = int(c.block.x) == p.nx && c.grid.x == 1 && p.nx % 64 == 0 && p.nx <= 512 &&
+                                    p.ny % int(c.block.y) == 0;
                 if constexpr (LAY == LAYOUT_AA_ODD || LAY == LAYOUT_AB) {
                     if (xstage) {
                         const size_t lds = (LAY == LAYOUT_AA_ODD ? 2 : 1) * size_t(xmove_count<L>()) * size_t(p.nx) *
-                                           sizeof(typename St::T);
+                                           size_t(c.block.y) * sizeof(typename St::T);
                         if (flags == 2) k_step<L, St, MODEL, LAY, 2, true><<<c.grid, c.block, lds, c.stream>>>(p);
                         else if (flags) k_step<L, St, MODEL, LAY, 1, true><<<c.grid, c.block, lds, c.stream>>>(p);
                         else k_step<L, St, MODEL, LAY, 0, true><<<c.grid, c.block, lds, c.stream>>>(p);

@@ -262,11 +262,12 @@ def test_aa_equals_ab_bitwise(storage, steps):
     assert np.array_equal(fa, fb) and np.array_equal(ua, ub)
 
 
-def _xstage_case(lattice, model):
-    """Rows of 256 nodes: one workgroup per row, so the AB and AA odd steps move the
-    x-moving populations through LDS (aligned loads, and in AA odd aligned stores, with the
-    one-node shift in LDS)."""
-    shape = (256, 9, 1) if lattice == S.D2Q9 else (256, 6, 4)
+def _xstage_case(lattice, model, nx=256):
+    """Rows of a multiple of 64 nodes, whole rows per workgroup, so the AB and AA odd steps
+    move the x-moving populations through LDS (aligned loads, and in AA odd aligned stores,
+    with the one-node shift in LDS).  256-node rows: one row per workgroup; the LBGK and MRT
+    steps with 4- and 8-byte elements take two 128-node or four 64-node rows."""
+    shape = (nx, 8, 1) if lattice == S.D2Q9 else (nx, 6, 4)
     g = (2e-5, -1e-5, 3e-5 if lattice == S.D3Q19 else 0.0)
     kw = dict(force=g, walls=True, tau=0.6)
     if model == S.MRT:
@@ -279,9 +280,9 @@ def _xstage_case(lattice, model):
 
 
 @pytest.mark.parametrize("model", [S.BGK, S.MRT, S.REG, S.SMAG])
-@pytest.mark.parametrize("lattice", [S.D2Q9, S.D3Q19])
-def test_x_staging_fp64(lattice, model):
-    check_f64(_xstage_case(lattice, model), 9)
+@pytest.mark.parametrize("lattice,nx", [(S.D2Q9, 256), (S.D3Q19, 256), (S.D2Q9, 64), (S.D3Q19, 128)])
+def test_x_staging_fp64(lattice, nx, model):
+    check_f64(_xstage_case(lattice, model, nx), 9)
 
 
 @pytest.mark.parametrize("storage,sr", [(P.LBM_F64, 0), (P.LBM_F32, 0), (P.LBM_F32S, 0), (P.LBM_BF16S, 1),
@@ -289,13 +290,13 @@ def test_x_staging_fp64(lattice, model):
 @pytest.mark.parametrize("model", [S.BGK, S.MRT, S.SMAG])
 def test_x_staging_bitwise(model, storage, sr):
     """The staged AB and AA odd steps give the same bits: walls and force, after odd and
-    even step counts, on both lattices."""
-    for lattice in (S.D2Q9, S.D3Q19):
-        c = _xstage_case(lattice, model)
+    even step counts, on both lattices, one and several rows per workgroup."""
+    for lattice, nx in ((S.D2Q9, 256), (S.D3Q19, 256), (S.D2Q9, 64), (S.D3Q19, 128)):
+        c = _xstage_case(lattice, model, nx)
         for steps in (1, 6, 7):
             fa, ra, ua = gpu_run(c, steps, storage, P.LBM_AB, sr)
             fb, rb, ub = gpu_run(c, steps, storage, P.LBM_AA, sr)
-            assert np.array_equal(fa, fb) and np.array_equal(ua, ub) and np.array_equal(ra, rb), (lattice, steps)
+            assert np.array_equal(fa, fb) and np.array_equal(ua, ub) and np.array_equal(ra, rb), (lattice, nx, steps)
 
 
 _POP_LAYOUTS = [
