@@ -185,6 +185,25 @@ __device__ __forceinline__ void pop_store_at(T *base, uint32_t S, int slot, cons
     }
 }
 
+// Aligned store of the lane's own x in row (y + dy, z + dz) of slot `slot`, with the
+// non-temporal hint (the staged x-moving stores of the AA odd step).
+template <bool BUF, class T>
+__device__ __forceinline__ void pop_store_own_x(T *base, uint32_t S, int slot, const Geo &g, int dy, int dz, T v) {
+    if constexpr (BUF || sizeof(T) == 2) {
+        T *row = base + (size_t(slot) * S + g.row_off(dy, dz));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, 0x7fffffff, 0x00020000);
+        const int off = int(uint32_t(g.x) * uint32_t(sizeof(T)));
+        if constexpr (sizeof(T) == 2) __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(short, v), rs, off, 0, 2);
+        else if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), rs, off, 0, 2);
+        else {
+            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off, 0, 2);
+        }
+    } else {
+        __builtin_nontemporal_store(v, pop_addr(base, S, slot, g, 0, dy, dz));
+    }
+}
+
 // Address of population slot `slot` at node x + (dx, dy, dz) in a copy.  In the step
 // kernels y and z are the same for the whole workgroup, so the slot and row part is a
 // scalar base.  For 2-byte elements the x part is added as a 32-bit byte offset, which
@@ -290,9 +309,9 @@ __host__ __device__ constexpr int xmove_count() {
 // after the collision lane x puts f*_i into LDS, and after a second barrier writes
 // position x of slot i from lane x - e_x.  Every location is still read and written on
 // behalf of the node that owns it in place, by the workgroup of that node's row, reads
-// before the first barrier and writes after the second.  Measured on the 256^3 vortex
-// (A/B of the two libraries on one box): AA odd +0.6% (FP32, FP64) and +5% (shifted
-// BF16) on the whole AA run.
+// before the first barrier and writes after the second.  A/B of the two libraries on one
+// box (GLUPS): 256^3 FP32 AB 40.1 -> 41.8, AA 41.1 -> 41.4; shifted BF16 AB 79.2 -> 83.8,
+// AA 82.0 -> 85.7; the FP32 duct (two 128-node rows per workgroup) 39.7 -> 40.3.
 template <class L, class St, int MODEL, int LAYOUT, int FLAGS, bool XSTAGE = false>
 __global__ __launch_bounds__(512) void k_step(StepParams p) {
     static_assert(!XSTAGE || LAYOUT == LAYOUT_AA_ODD || LAYOUT == LAYOUT_AB, "x staging: AB and AA odd steps");
@@ -319,8 +338,8 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     // nodes ran at 5.3-5.4 TB/s against 6.0 for 256).
     const bool active = x < p.nx && y < p.ny;
     const bool pad = LAYOUT == LAYOUT_AB && x >= p.nx && x < int(p.rpitch) && y < p.ny;
-    // with XSTAGE the launch holds exactly one row per workgroup: every lane is active and
-    // reaches the barriers
+    // with XSTAGE the launch holds whole rows per workgroup, every one inside the lattice:
+    // every lane is active and reaches the barriers
     if (XSTAGE || active || pad) {
         const Geo g = make_geo(active ? x : p.nx - 1, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
         Geo gs = g;  // where this lane stores (AB: its own x)
@@ -407,7 +426,7 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
                 } else {
                     const int xs = x - L::ex(i);
                     const T v = xout[xmove_index<L>(i) * p.nx + (xs < 0 ? xs + p.nx : (xs >= p.nx ? xs - p.nx : xs))];
-                    __builtin_nontemporal_store(v, pop_addr(dst, S, slot, g, 0, dy, dz));
+                    pop_store_own_x<false>(dst, S, slot, g, dy, dz, v);
                 }
             }
         } else {

@@ -180,6 +180,24 @@ def test_shan_chen_random_fp64(lattice, shape, psi):
     check_f64(c, 30)
 
 
+@pytest.mark.parametrize("psi", [0, 1])
+@pytest.mark.parametrize("lattice,shape", [(S.D2Q9, (128, 10, 1)), (S.D3Q19, (64, 12, 10))])
+def test_shan_chen_x_staging_fp64(lattice, shape, psi):
+    """Rows of 128 and 64 nodes, one per workgroup: the psi pass and the step shift the
+    x-moving populations through LDS (AB and AA odd)."""
+    c = random_case(lattice, S.SHANCHEN, *shape, tau=0.9, G=0.9, psi=psi, du=0.02, drho=0.05)
+    check_f64(c, 30)
+
+
+@pytest.mark.parametrize("storage", [P.LBM_F64, P.LBM_F32, P.LBM_F32S])
+def test_shan_chen_x_staging_bitwise(storage):
+    c = random_case(S.D3Q19, S.SHANCHEN, 64, 12, 10, tau=0.9, G=0.9, psi=1, du=0.02, drho=0.05)
+    for steps in (1, 6, 7):
+        fa, ra, ua = gpu_run(c, steps, storage, P.LBM_AB)
+        fb, rb, ub = gpu_run(c, steps, storage, P.LBM_AA)
+        assert np.array_equal(fa, fb) and np.array_equal(ua, ub) and np.array_equal(ra, rb), steps
+
+
 # ------------------------------------------------------------------ FP32 / shifted storage
 
 _C2_REF = {}
