@@ -189,6 +189,14 @@ __device__ __forceinline__ void neq_moments_add(NeqMoments<C> &q, int i, C fn) {
     if (L::ey(i) * L::ez(i) == -1) q.yz -= fn;
 }
 
+// The regularized collision fuses multiply-adds only where a source expression writes one
+// (contract(on)), never across statements.  The step is compiled in several forms
+// (layouts, the x staging), and across-statement fusing of this collision's products
+// (the shared 1/3 t of the stress deviator) depended on the code around it: one form of
+// the regularized BF16 step rounded one population to the neighbouring BF16 value, which
+// broke the bit-for-bit equality of the layouts.  The default is restored after it.
+#pragma clang fp contract(on)
+
 // Regularized LBGK (regularized LBM subsection): the non-equilibrium part is replaced by
 // w_i / (2 cs^4) (e_ia e_ib - cs^2 d_ab) Pi_ab, Pi_ab = sum_i fn_i (e_ia e_ib - cs^2 d_ab),
 // then relaxed as in LBGK: h* = heq + (1 - omega) h_reg.  No body force (the API rejects
@@ -225,6 +233,8 @@ __device__ __forceinline__ void collide_reg(const C *h, C *o, const StepParams &
     }
     conserve<L, C>(o, m.drho, m.jx, m.jy, m.jz);
 }
+
+#pragma clang fp contract(fast)
 
 // Smagorinsky LBGK (Smagorinsky subgrid subsection): Q_ab = sum_i e_ia e_ib fn_i and the
 // local relaxation time tau = tau0 + tau_t, tau_t = (sqrt(tau0^2 + 4 cs^-4 C_S^2 |Q|) -

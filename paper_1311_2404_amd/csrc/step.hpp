@@ -39,6 +39,8 @@
 //  - AA even step: every load (all aligned; +7% over none).
 //  - 2-byte elements: only in the AA even step, where every access is aligned (+13% on
 //    the BF16 256^3 step); elsewhere the hint costs them 3-4%.
+// Where a step stages its shifts along x in LDS (XSTAGE of k_step and of the Shan-Chen
+// kernels), the x-moving values are read and written on aligned segments, with the hint.
 template <class L, int LAYOUT, class T>
 __device__ __forceinline__ T pop_load(const T *ptr, int i) {
     if constexpr (sizeof(T) < 4) {
@@ -49,7 +51,6 @@ __device__ __forceinline__ T pop_load(const T *ptr, int i) {
     return __builtin_nontemporal_load(ptr);
 }
 #define LBM_LOAD(ptr, i) pop_load<L, LAYOUT>((ptr), (i))
-#define LBM_STORE(ptr, v) __builtin_nontemporal_store((v), (ptr))
 // Stores of population i.  The AA odd step writes x-moving populations one element off
 // the wave's 256-byte segment, so each wave leaves a partly written 64-byte sector at
 // both ends that the neighbouring wave completes.  Those stores go without the hint: the
@@ -59,7 +60,6 @@ __device__ __forceinline__ void pop_store(T *ptr, T v, int i) {
     if (LAYOUT == lbm::LAYOUT_AA_ODD && L::ex(i) != 0) *ptr = v;
     else __builtin_nontemporal_store(v, ptr);
 }
-#define LBM_STORE_POP(ptr, v, i) pop_store<L, LAYOUT>((ptr), (v), (i))
 
 namespace lbm {
 
@@ -233,21 +233,6 @@ __device__ __forceinline__ void canon_loc(int layout, int i, const Geo &g, int &
     }
 }
 
-// Where the post-collision value f*_i of node x is written.
-template <class L>
-__device__ __forceinline__ void post_loc(int layout, int i, const Geo &g, int &slot, uint32_t &node) {
-    if (layout == LAYOUT_AB) {
-        slot = i;
-        node = g.pa(0, 0, 0);
-    } else if (layout == LAYOUT_AA_EVEN) {
-        slot = opp(i);
-        node = g.pa(0, 0, 0);
-    } else {
-        slot = i;
-        node = g.pa(L::ex(i), L::ey(i), L::ez(i));
-    }
-}
-
 // Half-way bounce-back node (boundary-conditions subsection): a wet node whose
 // populations streamed in from wall nodes are missing; each takes the value of the
 // node's opposite population, i.e. what reached the node moving towards the wall is
@@ -312,9 +297,13 @@ __host__ __device__ constexpr int xmove_count() {
 // before the first barrier and writes after the second.  A/B of the two libraries on one
 // box (GLUPS): 256^3 FP32 AB 40.1 -> 41.8, AA 41.1 -> 41.4; shifted BF16 AB 79.2 -> 83.8,
 // AA 82.0 -> 85.7; the FP32 duct (two 128-node rows per workgroup) 39.7 -> 40.3.
-template <class L, class St, int MODEL, int LAYOUT, int FLAGS, bool XSTAGE = false>
+// XSTAGE: 0 none, 1 rows of exactly the workgroup's width, 2 rows shorter than it (lanes
+// past the row's end; only this form carries the per-lane gating, which measured ~10%
+// slower on the 16-bit steps where it is not needed).
+template <class L, class St, int MODEL, int LAYOUT, int FLAGS, int XSTAGE = 0>
 __global__ __launch_bounds__(512) void k_step(StepParams p) {
     static_assert(!XSTAGE || LAYOUT == LAYOUT_AA_ODD || LAYOUT == LAYOUT_AB, "x staging: AB and AA odd steps");
+    constexpr bool RAGGED = XSTAGE == 2;
     using T = typename St::T;
     using C = typename St::C;
     constexpr int Q = L::Q;
@@ -338,8 +327,10 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
     // nodes ran at 5.3-5.4 TB/s against 6.0 for 256).
     const bool active = x < p.nx && y < p.ny;
     const bool pad = LAYOUT == LAYOUT_AB && x >= p.nx && x < int(p.rpitch) && y < p.ny;
-    // with XSTAGE the launch holds whole rows per workgroup, every one inside the lattice:
-    // every lane is active and reaches the barriers
+    // with XSTAGE the launch holds whole rows per workgroup, every one inside the lattice,
+    // and every lane reaches the barriers; lanes past a row's end (when nx is not a whole
+    // number of waves) work on the row's last node, load nothing of their own x and store
+    // only where the plain step would (AB padding lanes)
     if (XSTAGE || active || pad) {
         const Geo g = make_geo(active ? x : p.nx - 1, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
         Geo gs = g;  // where this lane stores (AB: its own x)
@@ -354,23 +345,25 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         // in AA odd, written (xout)
         [[maybe_unused]] extern __shared__ unsigned char lds_x[];
         [[maybe_unused]] const int rows_lds = LAYOUT == LAYOUT_AA_ODD ? 2 : 1;
+        [[maybe_unused]] const int xw = RAGGED ? int(blockDim.x) : p.nx;  // LDS row stride (>= nx)
+        [[maybe_unused]] const int xr = RAGGED ? (active ? x : p.nx - 1) : x;  // the node this lane works on
         [[maybe_unused]] T *xin = reinterpret_cast<T *>(lds_x) +
-                                  size_t(MULTI_ROW ? threadIdx.y : 0) * rows_lds * xmove_count<L>() * p.nx;
-        [[maybe_unused]] T *xout = xin + xmove_count<L>() * p.nx;
+                                  size_t(MULTI_ROW ? threadIdx.y : 0) * rows_lds * xmove_count<L>() * xw;
+        [[maybe_unused]] T *xout = xin + xmove_count<L>() * xw;
         if constexpr (XSTAGE) {
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 int slot, dx, dy, dz;
                 canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
                 if (L::ex(i) == 0) raw[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
-                else xin[xmove_index<L>(i) * p.nx + x] = __builtin_nontemporal_load(pop_addr(src, S, slot, g, 0, dy, dz));
+                else if (!RAGGED || active) xin[xmove_index<L>(i) * xw + x] = __builtin_nontemporal_load(pop_addr(src, S, slot, g, 0, dy, dz));
             }
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 if (L::ex(i) == 0) continue;
-                const int xs = x - L::ex(i);
-                raw[i] = xin[xmove_index<L>(i) * p.nx + (xs < 0 ? xs + p.nx : (xs >= p.nx ? xs - p.nx : xs))];
+                const int xs = xr - L::ex(i);
+                raw[i] = xin[xmove_index<L>(i) * xw + (xs < 0 ? xs + p.nx : (xs >= p.nx ? xs - p.nx : xs))];
             }
         } else {
 #pragma unroll
@@ -415,21 +408,23 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         if constexpr (XSTAGE && LAYOUT == LAYOUT_AA_ODD) {
 #pragma unroll
             for (int i = 0; i < Q; i++)
-                if (L::ex(i) != 0) xout[xmove_index<L>(i) * p.nx + x] = out[i];
+                if (L::ex(i) != 0) xout[xmove_index<L>(i) * xw + x] = out[i];
             __syncthreads();
+            if (!RAGGED || active) {
 #pragma unroll
-            for (int i = 0; i < Q; i++) {
-                int slot, dx, dy, dz;
-                post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-                if (L::ex(i) == 0) {
-                    pop_store_at<L, LAYOUT>(dst, S, slot, g, dx, dy, dz, out[i], i);
-                } else {
-                    const int xs = x - L::ex(i);
-                    const T v = xout[xmove_index<L>(i) * p.nx + (xs < 0 ? xs + p.nx : (xs >= p.nx ? xs - p.nx : xs))];
-                    pop_store_own_x<false>(dst, S, slot, g, dy, dz, v);
+                for (int i = 0; i < Q; i++) {
+                    int slot, dx, dy, dz;
+                    post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
+                    if (L::ex(i) == 0) {
+                        pop_store_at<L, LAYOUT>(dst, S, slot, g, dx, dy, dz, out[i], i);
+                    } else {
+                        const int xs = x - L::ex(i);
+                        const T v = xout[xmove_index<L>(i) * xw + (xs < 0 ? xs + p.nx : (xs >= p.nx ? xs - p.nx : xs))];
+                        pop_store_own_x<false>(dst, S, slot, g, dy, dz, v);
+                    }
                 }
             }
-        } else {
+        } else if (!RAGGED || active || pad) {
 #pragma unroll
             for (int i = 0; i < Q; i++) {
                 int slot, dx, dy, dz;
@@ -454,16 +449,22 @@ hipError_t launch_k_step(int lattice, int storage, int sr, int layout, int flags
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
                 // the AB and AA odd steps stage their x shifts in LDS where a workgroup is whole
-                // rows (no padding lanes, every row of every workgroup inside the lattice)
-                const bool xstage = int(c.block.x) == p.nx && c.grid.x == 1 && p.nx % 64 == 0 && p.nx <= 512 &&
+                // rows (every row of every workgroup inside the lattice)
+                const bool xstage = c.grid.x == 1 && int(c.block.x) >= p.nx && c.block.x <= 512 &&
                                     p.ny % int(c.block.y) == 0;
                 if constexpr (LAY == LAYOUT_AA_ODD || LAY == LAYOUT_AB) {
                     if (xstage) {
-                        const size_t lds = (LAY == LAYOUT_AA_ODD ? 2 : 1) * size_t(xmove_count<L>()) * size_t(p.nx) *
-                                           size_t(c.block.y) * sizeof(typename St::T);
-                        if (flags == 2) k_step<L, St, MODEL, LAY, 2, true><<<c.grid, c.block, lds, c.stream>>>(p);
-                        else if (flags) k_step<L, St, MODEL, LAY, 1, true><<<c.grid, c.block, lds, c.stream>>>(p);
-                        else k_step<L, St, MODEL, LAY, 0, true><<<c.grid, c.block, lds, c.stream>>>(p);
+                        const size_t lds = (LAY == LAYOUT_AA_ODD ? 2 : 1) * size_t(xmove_count<L>()) *
+                                           size_t(c.block.x) * size_t(c.block.y) * sizeof(typename St::T);
+                        if (int(c.block.x) == p.nx) {
+                            if (flags == 2) k_step<L, St, MODEL, LAY, 2, 1><<<c.grid, c.block, lds, c.stream>>>(p);
+                            else if (flags) k_step<L, St, MODEL, LAY, 1, 1><<<c.grid, c.block, lds, c.stream>>>(p);
+                            else k_step<L, St, MODEL, LAY, 0, 1><<<c.grid, c.block, lds, c.stream>>>(p);
+                        } else {
+                            if (flags == 2) k_step<L, St, MODEL, LAY, 2, 2><<<c.grid, c.block, lds, c.stream>>>(p);
+                            else if (flags) k_step<L, St, MODEL, LAY, 1, 2><<<c.grid, c.block, lds, c.stream>>>(p);
+                            else k_step<L, St, MODEL, LAY, 0, 2><<<c.grid, c.block, lds, c.stream>>>(p);
+                        }
                         return hipGetLastError();
                     }
                 }

@@ -118,7 +118,14 @@ struct StF16S {
             v = __builtin_amdgcn_cvt_sr_f16_f32(v, h, rnd, false);
             return __builtin_bit_cast(uint16_t, v[0]);
         } else {
-            return __builtin_bit_cast(uint16_t, static_cast<_Float16>(h));
+            // The FP32 value is kept as such before the conversion.  The compiler would
+            // otherwise fold the conversion into the multiply-add that produced it
+            // (v_fma_mix, one rounding straight to F16 instead of FP32 then F16) in some
+            // instantiations of a step and not in others, which then differ by an F16 ulp.
+            // The empty asm only pins h to a register; it emits no instruction.
+            float hr = h;
+            asm("" : "+v"(hr));
+            return __builtin_bit_cast(uint16_t, static_cast<_Float16>(hr));
         }
     }
 };

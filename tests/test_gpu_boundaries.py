@@ -36,9 +36,9 @@ def cavity(lattice, model, nx, ny, nz, tau=0.58, u_lid=0.06):
 
 @pytest.mark.parametrize("model", [S.BGK, S.MRT, S.REG, S.SMAG])
 @pytest.mark.parametrize("lattice,shape", [(S.D2Q9, (130, 37, 1)), (S.D3Q19, (34, 21, 18)),
-                                           (S.D2Q9, (256, 21, 1)), (S.D3Q19, (256, 9, 7))])
+                                           (S.D2Q9, (256, 21, 1)), (S.D3Q19, (256, 9, 7)), (S.D3Q19, (62, 12, 7))])
 def test_cavity_fp64(model, lattice, shape):
-    """Rows of 256 nodes take the AB and AA odd steps that shift along x through LDS."""
+    """Rows of 256 and 62 nodes take the AB and AA odd steps that shift along x through LDS."""
     check_f64(cavity(lattice, model, *shape), 60)
 
 

@@ -284,8 +284,9 @@ def _xstage_case(lattice, model, nx=256):
     """Rows of a multiple of 64 nodes, whole rows per workgroup, so the AB and AA odd steps
     move the x-moving populations through LDS (aligned loads, and in AA odd aligned stores,
     with the one-node shift in LDS).  256-node rows: one row per workgroup; the LBGK and MRT
-    steps with 4- and 8-byte elements take two 128-node or four 64-node rows."""
-    shape = (nx, 8, 1) if lattice == S.D2Q9 else (nx, 6, 4)
+    steps with 4- and 8-byte elements take two 128-node or four 64-node rows; rows of 62 and
+    250 nodes leave lanes past the row's end in the workgroup."""
+    shape = (nx, 8, 1) if lattice == S.D2Q9 else (nx, 8 if nx % 64 else 6, 4)
     g = (2e-5, -1e-5, 3e-5 if lattice == S.D3Q19 else 0.0)
     kw = dict(force=g, walls=True, tau=0.6)
     if model == S.MRT:
@@ -298,23 +299,40 @@ def _xstage_case(lattice, model, nx=256):
 
 
 @pytest.mark.parametrize("model", [S.BGK, S.MRT, S.REG, S.SMAG])
-@pytest.mark.parametrize("lattice,nx", [(S.D2Q9, 256), (S.D3Q19, 256), (S.D2Q9, 64), (S.D3Q19, 128)])
+@pytest.mark.parametrize("lattice,nx", [(S.D2Q9, 256), (S.D3Q19, 256), (S.D2Q9, 64), (S.D3Q19, 128),
+                                        (S.D2Q9, 250), (S.D3Q19, 62)])
 def test_x_staging_fp64(lattice, nx, model):
     check_f64(_xstage_case(lattice, model, nx), 9)
 
 
 @pytest.mark.parametrize("storage,sr", [(P.LBM_F64, 0), (P.LBM_F32, 0), (P.LBM_F32S, 0), (P.LBM_BF16S, 1),
                                         (P.LBM_F16S, 0)])
-@pytest.mark.parametrize("model", [S.BGK, S.MRT, S.SMAG])
+@pytest.mark.parametrize("model", [S.BGK, S.MRT, S.REG, S.SMAG])
 def test_x_staging_bitwise(model, storage, sr):
     """The staged AB and AA odd steps give the same bits: walls and force, after odd and
     even step counts, on both lattices, one and several rows per workgroup."""
-    for lattice, nx in ((S.D2Q9, 256), (S.D3Q19, 256), (S.D2Q9, 64), (S.D3Q19, 128)):
+    for lattice, nx in ((S.D2Q9, 256), (S.D3Q19, 256), (S.D2Q9, 64), (S.D3Q19, 128), (S.D2Q9, 250), (S.D3Q19, 62)):
         c = _xstage_case(lattice, model, nx)
         for steps in (1, 6, 7):
             fa, ra, ua = gpu_run(c, steps, storage, P.LBM_AB, sr)
             fb, rb, ub = gpu_run(c, steps, storage, P.LBM_AA, sr)
             assert np.array_equal(fa, fb) and np.array_equal(ua, ub) and np.array_equal(ra, rb), (lattice, nx, steps)
+
+
+@pytest.mark.parametrize("model", [S.BGK, S.SMAG])
+def test_x_staging_ragged_rows_layouts_bitwise(model):
+    """Rows of 62 nodes in 64-lane workgroups: with the SoA layout and no padding the two
+    lanes past the row's end are no padding lanes and must not store; every population
+    layout gives the default layout's bits, AB and AA."""
+    c = _xstage_case(S.D3Q19, model, 62)
+    for st in (P.LBM_F64, P.LBM_F32, P.LBM_BF16S):
+        for lay in (P.LBM_AB, P.LBM_AA):
+            ref = gpu_run(c, 7, st, lay)
+            for pl in (dict(kind=P.LBM_POP_SOA, soa_pad=0), dict(kind=P.LBM_POP_SOA),
+                       dict(kind=P.LBM_POP_TILED, tile_rows=1), dict(kind=P.LBM_POP_TILED, row_pad=768, block_pad=2560)):
+                got = gpu_run(c, 7, st, lay, pop_layout=pl)
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b), (st, lay, pl)
 
 
 _POP_LAYOUTS = [
