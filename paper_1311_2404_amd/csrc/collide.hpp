@@ -12,6 +12,7 @@
 //         (entropic LBM subsection), solved in FP64
 //   SC  : two components, force -G psi_c(x) sum_i w_i psi_other(x+e_i) e_i (Shan-Chen
 //         subsection), common velocity, exact-difference-method forcing
+//   REG : regularized LBGK, SMAG: Smagorinsky LBGK (their subsections; below)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>

@@ -13,9 +13,10 @@
 //             Each thread reads and writes exactly the same locations, so the single
 //             copy is updated in place without races; after an odd step the layout is
 //             the plain one again.
-// Rows along x are contiguous (SoA f[q][z][y][x]); a workgroup covers whole x rows when
-// nx allows, so the +-1 shifted reads along x stay inside cache lines the same
-// workgroup also reads.
+// Rows along x are contiguous in both population layouts (row-interleaved tiles, the
+// default, and SoA f[q][z][y][x]); a workgroup covers whole x rows when nx allows, so
+// the shifts along x stay inside lines the same workgroup also reads (or go through LDS,
+// XSTAGE below).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -298,8 +299,8 @@ __host__ __device__ constexpr int xmove_count() {
 // box (GLUPS): 256^3 FP32 AB 40.1 -> 41.8, AA 41.1 -> 41.4; shifted BF16 AB 79.2 -> 83.8,
 // AA 82.0 -> 85.7; the FP32 duct (two 128-node rows per workgroup) 39.7 -> 40.3.
 // XSTAGE: 0 none, 1 rows of exactly the workgroup's width, 2 rows shorter than it (lanes
-// past the row's end; only this form carries the per-lane gating, which measured ~10%
-// slower on the 16-bit steps where it is not needed).
+// past the row's end).  Only form 2 carries the per-lane tests; on whole rows they cost
+// the 16-bit steps 11-18% (shifted BF16 at 256^3: AA 84.9 -> 75.4, AB 83.1 -> 70.8 GLUPS).
 template <class L, class St, int MODEL, int LAYOUT, int FLAGS, int XSTAGE = 0>
 __global__ __launch_bounds__(512) void k_step(StepParams p) {
     static_assert(!XSTAGE || LAYOUT == LAYOUT_AA_ODD || LAYOUT == LAYOUT_AB, "x staging: AB and AA odd steps");
@@ -350,6 +351,10 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         [[maybe_unused]] T *xin = reinterpret_cast<T *>(lds_x) +
                                   size_t(MULTI_ROW ? threadIdx.y : 0) * rows_lds * xmove_count<L>() * xw;
         [[maybe_unused]] T *xout = xin + xmove_count<L>() * xw;
+        // the node's flag is loaded ahead of the populations: after the staging barrier its
+        // latency would stand alone before the collision's branch (+2.4% on the FP32 duct,
+        // +2.9% FP64, +1.2% on the cavity's AB step)
+        const uint32_t fl = FLAGS ? p.flags[n] : 0u;
         if constexpr (XSTAGE) {
 #pragma unroll
             for (int i = 0; i < Q; i++) {
@@ -375,7 +380,6 @@ __global__ __launch_bounds__(512) void k_step(StepParams p) {
         }
         T out[Q];
         bool bad = false;
-        const uint32_t fl = FLAGS ? p.flags[n] : 0u;
         // equilibrium velocity nodes exist for the polynomial-equilibrium models
         const bool vel = FLAGS == 2 && fl == 2u;
         if (fl == 1u) {
