@@ -310,7 +310,9 @@ def test_x_staging_fp64(lattice, nx, model):
 @pytest.mark.parametrize("model", [S.BGK, S.MRT, S.REG, S.SMAG])
 def test_x_staging_bitwise(model, storage, sr):
     """The staged AB and AA odd steps give the same bits: walls and force, after odd and
-    even step counts, on both lattices, one and several rows per workgroup."""
+    even step counts, on both lattices, one and several rows per workgroup, whole and ragged
+    rows.  With 4-byte elements the AA odd step loads its x-moving values straight into LDS
+    and AB through registers, so the comparison also checks that load path."""
     for lattice, nx in ((S.D2Q9, 256), (S.D3Q19, 256), (S.D2Q9, 64), (S.D3Q19, 128), (S.D2Q9, 250), (S.D3Q19, 62)):
         c = _xstage_case(lattice, model, nx)
         for steps in (1, 6, 7):
