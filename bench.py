@@ -450,7 +450,7 @@ def main():
                          "timed at steps 1000 and 8000 (JSON line)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
+        print("bench.py measures one GPU: the library has no multi-GPU path (one process drives one device).",
               file=sys.stderr)
         sys.exit(2)
 
