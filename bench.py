@@ -422,8 +422,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--layout", choices=["ab", "aa"], default="aa",
-                    help="streaming layout of the timed step (AA: in place, even and odd kernels; AB: two copies)")
+    ap.add_argument("--layout", choices=["ab", "aa"], default="ab",
+                    help="streaming layout of the timed step (AB, the default: two copies; AA: in place, even "
+                         "and odd kernels)")
     ap.add_argument("--n", type=int, default=N_SIDE, help="lattice side (default 256)")
     ap.add_argument("--no-variants", action="store_true", help="time the FP32 run only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -558,7 +559,7 @@ def main():
             b2 = bytes_per_node(st)
             v = dict(mlups=round(m2, 1), bytes_per_node=b2, steps=vsteps, warmup=vwarm,
                      hbm_gbs_algorithmic=round(b2 * N / (k2 * 1e-3) / 1e9, 1))
-            # the same storage with the other streaming layout (16-bit steps are faster in AB)
+            # the same storage with the other streaming layout (the 16-bit steps are faster in AA)
             other = P.LBM_AB if layout == P.LBM_AA else P.LBM_AA
             w3, _ = timed(st, vsteps, vwarm, other)
             v["mlups_" + ("ab" if other == P.LBM_AB else "aa")] = round(N * vsteps / w3 / 1e6, 1)

@@ -105,7 +105,9 @@ int lbm_set_storage(lbm_sim *sim, int storage, int layout, int stochastic_round)
  *  - LBM_POP_TILED (default): f[z][y/TY][c][q][y%TY][x].  Each x row of each population
  *    is a run of nx elements rounded up to 256 bytes, plus row_pad bytes; the C*Q runs of
  *    TY = tile_rows consecutive rows lie together, followed by block_pad bytes.
- *    tile_rows 0 means 8; otherwise a power of two from 1 to 64.  block_pad -1 means
+ *    tile_rows 0 picks the largest power of two up to 64 whose run of TY rows holds at
+ *    most 32 KB (32 rows at nx = 256 in FP32, 16 in FP64, 64 in BF16); otherwise a
+ *    power of two from 1 to 64.  block_pad -1 means
  *    1024.  TY is halved while half of it still covers ny.  Grids whose tiled layout
  *    would not fit 32-bit element offsets fall back to LBM_POP_SOA.
  *  - LBM_POP_SOA: the structure of arrays f[c][q][z][y][x] of the paper's GPU data

@@ -99,7 +99,7 @@ int hip_fail(lbm_sim *s, hipError_t e, const char *where) {
         if (e_ != hipSuccess) return hip_fail(sim, e_, #expr); \
     } while (0)
 
-constexpr int POP_TILE_LOG2_DEFAULT = 3;  // rows per population run of the tiled layout: 2^this
+constexpr uint64_t POP_RUN_BYTES_DEFAULT = 32768;  // default tile height: runs of at most this many bytes
 
 size_t elem_size(int storage) {
     switch (storage) {
@@ -187,10 +187,15 @@ StepParams base_params(const lbm_sim *s) {
 }
 
 // Population layout.  Two are built:
-//  - row-interleaved, f[z][y/TY][c][q][y%TY][x] (TY = 2^tyl rows per tile, 8 by default;
+//  - row-interleaved, f[z][y/TY][c][q][y%TY][x] (TY = 2^tyl rows per tile; by default the
+//    largest power of two up to 64 whose run of TY rows holds at most 32 KB: 32 rows at
+//    nx = 256 in FP32, 16 in FP64, 64 in BF16.  Against 8-row tiles, A/B on one box:
+//    FP32 256^3 AA -1.2% and AB -2.6% per step, FP64 -2.6% / -1.6%, BF16 -0.9% / -0.7%,
+//    the 128-wide duct FP32 -1.6% / -1.3% and FP64 -2.1% / -1.6%, the 254^3 cavity
+//    -2.4% / -1.8%; 16 KB runs were slower than 8 KB ones at nx = 256 in FP32.
 //    ceil(ny/TY) tiles per z plane, the last one padded with rows that are never
 //    addressed when TY does not divide ny: 254 rows cost 0.8% more memory and keep the
-//    8-row tiles, which a 2-row tiling (the largest power of two dividing 254) lost:
+//    tiling, which a 2-row tiling (the largest power of two dividing 254) lost:
 //    33.8 against 39.5 GLUPS at 254^3):
 //    each x row of every population is a run of RP
 //    elements (nx rounded up to 256 bytes), and the C Q runs of one row lie together, so
@@ -210,7 +215,12 @@ void pop_geometry(lbm_sim *s) {
     const uint64_t align = 256 / elem_size(s->storage);
     const uint64_t cq = uint64_t(s->C) * s->Q;
     const uint64_t RP = (uint64_t(s->nx) + align - 1) / align * align + uint64_t(s->row_pad) / 256 * align;
-    int tyl = s->pop_tyl >= 0 ? s->pop_tyl : POP_TILE_LOG2_DEFAULT;
+    int tyl = s->pop_tyl;
+    if (tyl < 0) {
+        const uint64_t row_bytes = RP * elem_size(s->storage);
+        tyl = 0;
+        while (tyl < 6 && (row_bytes << (tyl + 1)) <= POP_RUN_BYTES_DEFAULT) tyl++;
+    }
     while (tyl > 0 && (1 << (tyl - 1)) >= s->ny) tyl--;
     const uint64_t ty = uint64_t(1) << tyl, tiles = (uint64_t(s->ny) + ty - 1) / ty * s->nz;
     const uint64_t block_pad = s->block_pad >= 0 ? uint64_t(s->block_pad) : 1024;

@@ -125,7 +125,8 @@ C2_REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_
 
 
 @pytest.mark.parametrize("storage,layout,tol", [(P.LBM_F64, P.LBM_AA, 1e-12), (P.LBM_F64, P.LBM_AB, 1e-12),
-                                                (P.LBM_F32, P.LBM_AA, 1e-5), (P.LBM_F32S, P.LBM_AA, 1e-5)])
+                                                (P.LBM_F32, P.LBM_AB, 1e-5), (P.LBM_F32, P.LBM_AA, 1e-5),
+                                                (P.LBM_F32S, P.LBM_AA, 1e-5)])
 def test_c2_fullsize_1000_steps_vs_oracle(storage, layout, tol):
     """The metric's configuration itself, 256^3 for its 1000 steps, against the FP64
     oracle's own run of it (stored by tests/golden/make_c2_reference.py, which calls
