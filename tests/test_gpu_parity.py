@@ -379,6 +379,19 @@ def test_population_layouts_agree_bitwise(model):
                     assert np.array_equal(a, b), (model, st, lay, pl)
 
 
+def test_default_tiles_several_per_plane_bitwise():
+    """The default tile height gives each population run up to 32 KB and 64 rows: 64 rows of
+    64 nodes in FP32, FP64 and BF16 here, so with ny = 80 a z plane holds two tiles, the second
+    padded.  The fields equal those of the SoA layout bit for bit, AB and AA."""
+    c = random_case(S.D3Q19, S.BGK, 64, 80, 3, force=(2e-5, -1e-5, 0), walls=True)
+    for st in (P.LBM_F64, P.LBM_F32, P.LBM_BF16S):
+        for lay in (P.LBM_AB, P.LBM_AA):
+            ref = gpu_run(c, 5, st, lay, pop_layout=dict(kind=P.LBM_POP_SOA))
+            got = gpu_run(c, 5, st, lay)
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), (st, lay)
+
+
 def test_pop_layout_only_before_init():
     s = P.Sim(S.D3Q19, S.BGK, 8, 8, 8, 0.7)
     P.lbm_set_pop_layout(s.h, P.LBM_POP_SOA)
