@@ -344,8 +344,8 @@ def run_extras(P, S, stream, torch):
     # 64x256 grid run to the steady state, against the sharp-interface solution
     fe = {}
     cs = S.spinodal()
-    for st, tag in [(P.LBM_F32S, "f32s"), (P.LBM_F32, "f32")]:
-        s = P.Sim.from_case(cs, st, P.LBM_AB, stream=stream)
+    for st, tag, lay in [(P.LBM_F32S, "f32s", P.LBM_AB), (P.LBM_F32, "f32", P.LBM_AB), (P.LBM_F32S, "f32s_aa", P.LBM_AA)]:
+        s = P.Sim.from_case(cs, st, lay, stream=stream)
         s.step(20)
         ms = _time_steps(s, stream, torch, 200)
         d = s.diag()
