@@ -37,25 +37,47 @@ __device__ __forceinline__ void fe_complete(C *v, const StepParams &p, const Geo
 // phi = sum_i g_i of the populations streaming into x (completed on half-way nodes); the
 // g lattice is stored plain in every storage (its equilibria are O(phi, mu), not centred
 // on w_i, so g - w_i would only lose digits)
-template <class L, class St, int LAYOUT, bool FLAGS>
+// XS (AB only): 0 none; 1 rows of exactly the workgroup's width, 2 rows shorter than it.  The
+// x-moving populations are loaded on aligned segments into LDS and taken from x - e_x
+// there, as in the polynomial-equilibrium step; lanes past a row's end load nothing of
+// their own x and leave after the barrier.
+template <class L, class St, int LAYOUT, bool FLAGS, int XS = 0>
 __global__ __launch_bounds__(512) void k_fe_phi(StepParams p) {
+    static_assert(!XS || LAYOUT == LAYOUT_AB, "x staging: AB");
     using T = typename St::T;
     using C = typename St::C;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const int z = blockIdx.z;
-    if (x >= p.nx || y >= p.ny) return;
-    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+    const bool active = x < p.nx && y < p.ny;
+    if (!XS && !active) return;
+    const Geo g = make_geo(active ? x : p.nx - 1, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
     const uint32_t n = g.at(0, 0, 0);
     const T *gs = static_cast<const T *>(p.src) + size_t(L::Q) * p.S;
+    [[maybe_unused]] extern __shared__ unsigned char lds_x[];
+    [[maybe_unused]] T *xin = reinterpret_cast<T *>(lds_x);
+    [[maybe_unused]] const int xw = XS == 2 ? int(blockDim.x) : p.nx;
+    const bool hw = FLAGS && p.flags[n] == 3;
     C v[L::Q];
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
         int slot, dx, dy, dz;
         canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        v[i] = C(LBM_LOAD(pop_addr(gs, p.S, slot, g, dx, dy, dz), i));
+        if (!XS || L::ex(i) == 0) v[i] = C(LBM_LOAD(pop_addr(gs, p.S, slot, g, dx, dy, dz), i));
+        else if (XS == 1 || active) xin[xmove_index<L>(i) * xw + x] = __builtin_nontemporal_load(pop_addr(gs, p.S, slot, g, 0, dy, dz));
     }
-    if (FLAGS && p.flags[n] == 3) fe_complete<L, C>(v, p, g);
+    if constexpr (XS != 0) {
+        __syncthreads();
+        const int xr = active ? x : p.nx - 1;
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            if (L::ex(i) == 0) continue;
+            const int xs = xr - L::ex(i);
+            v[i] = C(xin[xmove_index<L>(i) * xw + (xs < 0 ? xs + p.nx : (xs >= p.nx ? xs - p.nx : xs))]);
+        }
+        if (!active) return;
+    }
+    if (hw) fe_complete<L, C>(v, p, g);
     C r = C(0);
 #pragma unroll
     for (int i = 0; i < L::Q; i++) r += v[i];
@@ -67,29 +89,58 @@ __global__ __launch_bounds__(512) void k_fe_phi(StepParams p) {
 // (A(...) - kappa phi lap + rho e.u + ...) + gradient terms, so no O(1) value is formed
 // and a shifted storage keeps the small O(F) and O(u) parts.  g is computed and stored
 // plain (k = g): its values are O(phi, mu) themselves.
-template <class L, class St, int LAYOUT, bool FLAGS>
+// XS as for k_fe_phi.  AB steps on padded rows: lanes past the row's end run the step on the
+// row's last node and store into the row's padding, which is never read, so every store
+// instruction writes whole memory sectors (as the polynomial-equilibrium step does).
+template <class L, class St, int LAYOUT, bool FLAGS, int XS = 0>
 __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
+    static_assert(!XS || LAYOUT == LAYOUT_AB, "x staging: AB");
     using T = typename St::T;
     using C = typename St::C;
-    constexpr int Q = L::Q;
+    constexpr int Q = L::Q, NXM = xmove_count<L>();
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const int z = blockIdx.z;
-    if (x >= p.nx || y >= p.ny) return;
-    const Geo g = make_geo(x, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+    const bool active = x < p.nx && y < p.ny;
+    const bool pad = LAYOUT == LAYOUT_AB && x >= p.nx && x < int(p.rpitch) && y < p.ny;
+    if (!XS && !active && !pad) return;
+    const Geo g = make_geo(active ? x : p.nx - 1, y, z, p.nx, p.ny, p.nz, p.rp, p.rpitch, p.tyl);
+    Geo gs = g;  // where this lane stores in AB (its own x)
+    gs.x = x;
     const uint32_t n = g.at(0, 0, 0), S = p.S;
     const T *src = static_cast<const T *>(p.src);
     T *dst = static_cast<T *>(p.dst);
     const C *__restrict__ phis = static_cast<const C *>(p.psi);
+    [[maybe_unused]] extern __shared__ unsigned char lds_x[];
+    [[maybe_unused]] T *xin = reinterpret_cast<T *>(lds_x);
+    [[maybe_unused]] const int xw = XS == 2 ? int(blockDim.x) : p.nx;
+    const uint32_t fl = FLAGS ? p.flags[n] : 0u;
     T rf[Q], rg[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         int slot, dx, dy, dz;
         canon_dir<L>(LAYOUT, i, slot, dx, dy, dz);
-        rf[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
-        rg[i] = LBM_LOAD(pop_addr(src, S, Q + slot, g, dx, dy, dz), i);
+        if (!XS || L::ex(i) == 0) {
+            rf[i] = LBM_LOAD(pop_addr(src, S, slot, g, dx, dy, dz), i);
+            rg[i] = LBM_LOAD(pop_addr(src, S, Q + slot, g, dx, dy, dz), i);
+        } else if (XS == 1 || active) {
+            xin[xmove_index<L>(i) * xw + x] = __builtin_nontemporal_load(pop_addr(src, S, slot, g, 0, dy, dz));
+            xin[(NXM + xmove_index<L>(i)) * xw + x] = __builtin_nontemporal_load(pop_addr(src, S, Q + slot, g, 0, dy, dz));
+        }
     }
-    const uint32_t fl = FLAGS ? p.flags[n] : 0u;
+    if constexpr (XS != 0) {
+        __syncthreads();
+        const int xr = active ? x : p.nx - 1;
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            if (L::ex(i) == 0) continue;
+            const int xs = xr - L::ex(i);
+            const int xi = xs < 0 ? xs + p.nx : (xs >= p.nx ? xs - p.nx : xs);
+            rf[i] = xin[xmove_index<L>(i) * xw + xi];
+            rg[i] = xin[(NXM + xmove_index<L>(i)) * xw + xi];
+        }
+        if (!active && !pad) return;
+    }
     T of[Q], og[Q];
     bool bad = false;
     if (fl == 1u) {
@@ -184,10 +235,17 @@ __global__ __launch_bounds__(512) void k_step_fe(StepParams p) {
         int slot, dx, dy, dz;
         post_dir<L>(LAYOUT, i, slot, dx, dy, dz);
         // buffer-descriptor stores in AB (+0.9% on the spinodal case; AA measured 0.6% slower)
-        pop_store_at<L, LAYOUT, LAYOUT == LAYOUT_AB>(dst, S, slot, g, dx, dy, dz, of[i], i);
-        pop_store_at<L, LAYOUT, LAYOUT == LAYOUT_AB>(dst, S, Q + slot, g, dx, dy, dz, og[i], i);
+        const Geo &gw = LAYOUT == LAYOUT_AB ? gs : g;
+        pop_store_at<L, LAYOUT, LAYOUT == LAYOUT_AB>(dst, S, slot, gw, dx, dy, dz, of[i], i);
+        pop_store_at<L, LAYOUT, LAYOUT == LAYOUT_AB>(dst, S, Q + slot, gw, dx, dy, dz, og[i], i);
     }
     raise_divergence(p, bad);
+}
+
+// The AB kernels stage their x shifts in LDS where a workgroup is one whole row (every row
+// of every workgroup inside the lattice; one row per workgroup).
+bool fe_xstage(const StepParams &p, const LaunchCfg &c) {
+    return c.grid.x == 1 && c.block.y == 1 && int(c.block.x) >= p.nx && c.block.x <= 512;
 }
 
 }  // namespace
@@ -199,6 +257,19 @@ hipError_t launch_fe_phi(int lattice, int storage, int layout, bool flags, const
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
+                if constexpr (LAY == LAYOUT_AB) {
+                    if (fe_xstage(p, c)) {
+                        const size_t lds = size_t(xmove_count<L>()) * c.block.x * c.block.y * sizeof(typename St::T);
+                        if (int(c.block.x) == p.nx) {
+                            if (flags) k_fe_phi<L, St, LAY, true, 1><<<c.grid, c.block, lds, c.stream>>>(p);
+                            else k_fe_phi<L, St, LAY, false, 1><<<c.grid, c.block, lds, c.stream>>>(p);
+                        } else {
+                            if (flags) k_fe_phi<L, St, LAY, true, 2><<<c.grid, c.block, lds, c.stream>>>(p);
+                            else k_fe_phi<L, St, LAY, false, 2><<<c.grid, c.block, lds, c.stream>>>(p);
+                        }
+                        return hipGetLastError();
+                    }
+                }
                 if (flags) k_fe_phi<L, St, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
                 else k_fe_phi<L, St, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
                 return hipGetLastError();
@@ -215,6 +286,19 @@ hipError_t launch_step_fe(int lattice, int storage, int layout, bool flags, cons
             using St = decltype(st);
             return with_layout(layout, [&](auto lay) {
                 constexpr int LAY = decltype(lay)::value;
+                if constexpr (LAY == LAYOUT_AB) {
+                    if (fe_xstage(p, c)) {
+                        const size_t lds = 2 * size_t(xmove_count<L>()) * c.block.x * c.block.y * sizeof(typename St::T);
+                        if (int(c.block.x) == p.nx) {
+                            if (flags) k_step_fe<L, St, LAY, true, 1><<<c.grid, c.block, lds, c.stream>>>(p);
+                            else k_step_fe<L, St, LAY, false, 1><<<c.grid, c.block, lds, c.stream>>>(p);
+                        } else {
+                            if (flags) k_step_fe<L, St, LAY, true, 2><<<c.grid, c.block, lds, c.stream>>>(p);
+                            else k_step_fe<L, St, LAY, false, 2><<<c.grid, c.block, lds, c.stream>>>(p);
+                        }
+                        return hipGetLastError();
+                    }
+                }
                 if (flags) k_step_fe<L, St, LAY, true><<<c.grid, c.block, 0, c.stream>>>(p);
                 else k_step_fe<L, St, LAY, false><<<c.grid, c.block, 0, c.stream>>>(p);
                 return hipGetLastError();
